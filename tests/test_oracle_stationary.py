@@ -1,0 +1,127 @@
+"""Statistical and closed-form pins of the oracle's noise, steady state and
+two-time correlation."""
+import numpy as np
+import pytest
+
+from oracle import closed_forms, lindblad, observables, philox, pump, twa
+
+
+def test_pump_noise_covariance_equals_w():
+    """<chi_i chi_j> dt = w_ij dt and <xi xi> dt = Gamma dt (Eq. (S1) noise law)."""
+    n, w, alpha, B = 6, 1.7, 0.8, 4000
+    p = pump.build_pump(n, w, alpha)
+    samples, coll = [], []
+    for step in range(60):
+        zx, zy = philox.pump_noise(11, step, B, n)
+        samples.append(zx @ p.F.T)
+        samples.append(zy @ p.F.T)
+        gx, gy = philox.collective_noise(11, step, B)
+        coll.append(gx)
+        coll.append(gy)
+    X = np.concatenate(samples)
+    M = X.shape[0]
+    C = X.T @ X / M
+    se = np.sqrt((np.outer(np.diag(p.W), np.diag(p.W)) + p.W ** 2) / M)
+    assert np.all(np.abs(C - p.W) < 4.5 * se)
+    g = np.concatenate(coll)
+    assert abs(g.var() - 1.0) < 4.5 * np.sqrt(2.0 / g.size)
+
+
+def test_lindblad_collective_steady_state_is_detailed_balance():
+    """Brute-force Eq. (1) at alpha = 0 from the all-up state relaxes to the
+    detailed-balance populations quoted in the SM (collective pump)."""
+    n, gamma, w = 4, 1.0, 0.6
+    W = pump.pump_matrix(n, w, 0.0)
+    rho = lindblad.steady_state(W, gamma, n, lindblad.product_state(n, True))
+    ops = lindblad.operators(n)
+    Sz = sum(ops[2])
+    Sp = sum(ops[0])
+    Sm = sum(ops[1])
+    sz = lindblad.expect(rho, Sz).real
+    spsm = lindblad.expect(rho, Sp @ Sm).real
+    g2 = lindblad.expect(rho, Sp @ Sp @ Sm @ Sm).real / spsm ** 2
+    ez, es, eg = closed_forms.dicke_alpha0(n, gamma, w)
+    assert abs(sz - ez) < 1e-8 and abs(spsm - es) < 1e-8 and abs(g2 - eg) < 1e-8
+
+
+def test_alpha0_stationary_law_monte_carlo():
+    """alpha = 0, w = Gamma/2, N = 10: the Monte Carlo of Eq. (S1) approaches the
+    exact stationary law of the rigidly rotating collective spin.  Heun's
+    first-order length drift biases the moments by about 2 % at dt = 1e-3."""
+    n, gamma, w = 10, 1.0, 0.5
+    exact = closed_forms.stationary_alpha0(n, gamma, w)
+    ez, es, eg = observables.derived(exact)
+    assert abs(ez + 7.940) < 1e-3 and abs(es - 7.940) < 1e-3 and abs(eg - 1.519) < 1e-3
+    cfg = twa.RunConfig(n_spin=n, w=w, alpha=0.0, n_traj=1024, dt=1e-3, n_steps=3000,
+                        seed=2, burnin=1000)
+    m = observables.finalize(twa.run(cfg).traj_moments)
+    for key, ref in (("Sz", ez), ("SpSm", es), ("g2", eg)):
+        tol = 4 * m[key + "_se"] + 0.04 * abs(ref)
+        assert abs(m[key] - ref) < tol, (key, m[key], ref, m[key + "_se"])
+
+
+def test_alpha0_w_equals_gamma_intensity_is_dicke():
+    """At w = Gamma the law is uniform: <S+S-> = (N^2 + 2N)/6 (quantum Dicke value)."""
+    n = 8
+    exact = closed_forms.stationary_alpha0(n, 1.0, 1.0)
+    assert abs(observables.derived(exact)[1] - (n * n + 2 * n) / 6.0) < 1e-10
+    assert abs(closed_forms.dicke_alpha0(n, 1.0, 1.0)[1] - (n * n + 2 * n) / 6.0) < 1e-10
+    cfg = twa.RunConfig(n_spin=n, w=1.0, alpha=0.0, n_traj=1024, dt=1e-3, n_steps=2500,
+                        seed=5, burnin=1000)
+    m = observables.finalize(twa.run(cfg).traj_moments)
+    assert abs(m["SpSm"] - (n * n + 2 * n) / 6.0) < 4 * m["SpSm_se"] + 0.04 * (n * n + 2 * n) / 6.0
+    assert abs(m["Sz"]) < 4 * m["Sz_se"] + 0.05
+
+
+def test_two_time_alpha0_decays_at_gamma():
+    """alpha = 0, w = Gamma: the drift vanishes, S diffuses rigidly and both the
+    symmetric correlation and the response decay as exp(-Gamma t); the
+    spectrum of the symmetric part has FWHM 2 Gamma (SM, collective pump)."""
+    n = 6
+    cfg = twa.RunConfig(n_spin=n, w=1.0, alpha=0.0, n_traj=768, dt=2e-3, n_steps=1500 + 1000,
+                        seed=8, burnin=1500, n_lags=100, lag_stride=10)
+    r = twa.run(cfg)
+    csym, chi, _ = observables.two_time(r.corr_blocks, r.chi_blocks, cfg.n_traj)
+    t = np.arange(100) * 10 * cfg.dt
+    sel = t <= 1.0
+    rate_c = -np.polyfit(t[sel], np.log(csym.real[sel]), 1)[0]
+    rate_x = -np.polyfit(t[sel], np.log(chi[0][sel]), 1)[0]
+    assert abs(rate_c - 1.0) < 0.15 and abs(rate_x - 1.0) < 0.1
+    assert abs(chi[0][0] - n) < 1e-12 and abs(chi[3][0] - n) < 1e-12
+    # symmetric part at lag 0 equals the intensity estimator at t0
+    assert np.all(np.abs(csym.imag) < 0.2 * np.abs(csym.real[0]))
+
+
+def test_response_fd_matches_tangent():
+    base = dict(n_spin=5, w=2.0, alpha=1.0, n_traj=16, dt=1e-3, n_steps=200, seed=3,
+                burnin=100, n_lags=10, lag_stride=10)
+    rt = twa.run(twa.RunConfig(**base))
+    rf = twa.run(twa.RunConfig(response_eps=1e-6, **base))
+    assert np.allclose(rf.chi_blocks, rt.chi_blocks, rtol=0, atol=2e-4 * np.abs(rt.chi_blocks).max())
+    assert np.array_equal(rf.corr_blocks, rt.corr_blocks)
+
+
+def test_csym_lag0_equals_intensity_at_origin():
+    cfg = twa.RunConfig(n_spin=4, w=1.0, alpha=0.5, n_traj=32, dt=1e-3, n_steps=20, seed=1,
+                        burnin=20, n_lags=1)
+    r = twa.run(cfg)
+    t2 = twa.moments(r.final_state)[:, 0]
+    assert np.isclose(r.corr_blocks.sum(), t2.sum(), rtol=1e-14)
+
+
+def test_spectrum_of_exponential_has_fwhm_two_gamma():
+    tau, L, g = 0.01, 4096, 0.7
+    corr = np.exp(-g * tau * np.arange(L)).astype(np.complex128)
+    om, S = observables.spectrum(corr, tau)
+    assert abs(observables.fwhm(om, S) - 2 * g) < 0.01 * 2 * g
+    # peak height 2/g of the Lorentzian 2 g / (g^2 + omega^2)
+    assert abs(S.max() - 2.0 / g) < 0.01 * 2.0 / g
+
+
+def test_jackknife_se_of_mean_matches_block_standard_error():
+    rng = np.random.default_rng(0)
+    x = rng.normal(size=(256, 5))
+    out = observables.finalize(x)
+    bm = x.reshape(32, 8, 5).mean(1)
+    for j, name in enumerate(observables.MOMENT_NAMES):
+        assert np.isclose(out[name + "_se"], bm[:, j].std(ddof=1) / np.sqrt(32), rtol=1e-10)
