@@ -10,8 +10,10 @@ Test infrastructure only; see the package docstring.
   w (2 eta(alpha) - 1), eta the Dirichlet eta function.
 * Eq. (S1) noise: <chi_i chi_j> = w_ij.  Any F with F F^T = W has that law; the
   reading used on both sides is the unique symmetric positive-semidefinite
-  square root F = V diag(sqrt(max(lambda, 0))) V^T, defined also at alpha = 0
-  where W has rank one.
+  square root F = V diag(sqrt(lambda+)) V^T, defined also at alpha = 0 where W
+  has rank one; lambda+ is lambda where lambda > 8 N eps lambda_max (eps the
+  binary64 unit round-off) and 0 otherwise, so that round-off eigenvalues of
+  the rank-one case do not leak sqrt(eps)-sized noise into F.
 """
 from __future__ import annotations
 
@@ -53,7 +55,9 @@ def build_pump(n_spin: int, w: float, alpha: float) -> Pump:
         raise ValueError("need N >= 1, finite w >= 0, finite alpha >= 0")
     W = pump_matrix(n_spin, w, alpha)
     lam, V = np.linalg.eigh(W)
-    lam_c = np.clip(lam, 0.0, None)          # round-off negatives (rank-one alpha=0)
+    # eigenvalues within round-off of zero (the rank-one alpha = 0 case) are zero
+    tol = 8.0 * n_spin * np.finfo(np.float64).eps * max(float(lam[-1]), 0.0)
+    lam_c = np.where(lam > tol, lam, 0.0)
     F = (V * np.sqrt(lam_c)) @ V.T
     F = 0.5 * (F + F.T)
     return Pump(n_spin, float(w), float(alpha), W, F, lam, V, float(lam[0]), float(lam[-1]))
@@ -85,7 +89,8 @@ def dfactor(p: Pump, dW: np.ndarray) -> np.ndarray:
     Sylvester equation is diagonal: X'_ij = (V^T dW V)_ij / (r_i + r_j),
     set to zero where r_i + r_j = 0.
     """
-    r = np.sqrt(np.clip(p.lam, 0.0, None))
+    tol = 8.0 * p.n_spin * np.finfo(np.float64).eps * max(p.lam_max, 0.0)
+    r = np.sqrt(np.where(p.lam > tol, p.lam, 0.0))
     B = p.V.T @ dW @ p.V
     den = r[:, None] + r[None, :]
     Xp = np.where(den > 0, B / np.where(den > 0, den, 1.0), 0.0)
