@@ -1,0 +1,291 @@
+/*
+ * twa.h -- C ABI of the MI355X (gfx950) engine for the dissipative
+ * Truncated-Wigner (TWA) trajectories of a chain of N two-level atoms under
+ * collective cavity decay Gamma and the correlated incoherent pump
+ * w_ij = w / (1 + |i - j|)^alpha.
+ *
+ * Paper: Chelpanova, Stefanini, O'Keeffe, Marino, "Phase diagram of lasing
+ * under correlated pump from GPU-accelerated Truncated Wigner dynamics".
+ *   - Model: Lindblad equation Eq. (1), pump profile Eq. (2), channel
+ *     decomposition and normalised pump (text after Eq. (2) and Eq. (3)).
+ *   - Method: SM Sec. S1 -- classical spins, the stochastic equations of
+ *     motion Eq. (S1), discrete initial sampling, trajectory averages, the
+ *     normal-ordering conversions (step 6 and Eq. (S2)), the two-time
+ *     decomposition Eq. (S3) with the three-copy response, and time
+ *     averaging over the window.
+ *   - Observables and g2: main text, "Observables and method".
+ *
+ * Conventions for every entry point:
+ *   - Return value 0 on success, a negative TWA_E* code on failure; no C++
+ *     exception crosses this boundary.  twa_last_error() returns a
+ *     thread-local message describing the last failure of the calling thread.
+ *   - Pointers documented as "host" are ordinary CPU memory owned by the
+ *     caller; pointers documented as "device" are HIP device memory owned by
+ *     the caller.  Library-owned objects (twa_pump) are released with their
+ *     free function.
+ *   - `stream` arguments are hipStream_t passed as void* (NULL = the null
+ *     stream).  Every compute entry point is stream-ordered on that stream
+ *     and returns after its results are on the host unless stated otherwise.
+ *   - All arithmetic of the time stepping runs in the library's HIP kernels
+ *     for gfx950.  There is no CPU fallback: without a usable GPU every
+ *     compute entry point returns TWA_EHIP.
+ */
+#ifndef TWA_H
+#define TWA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TWA_API __attribute__((visibility("default")))
+
+/* ---- status codes ---------------------------------------------------- */
+#define TWA_OK          0
+#define TWA_EINVAL     -1   /* an argument is out of range or inconsistent     */
+#define TWA_ENOMEM     -2   /* device or host allocation failed                */
+#define TWA_EHIP       -3   /* a HIP / rocSOLVER / rocBLAS call failed         */
+#define TWA_ENOTPSD    -4   /* pump matrix has a negative eigenvalue below     */
+                            /* -1e-10 * lambda_max (Eq. (2) is PSD; this flags */
+                            /* a non-PSD dense matrix)                         */
+#define TWA_EUNSTABLE  -5   /* NaN/Inf in the state or accumulators; outputs   */
+                            /* are still written so they can be inspected      */
+
+/* ---- precisions of the channel-mixing contraction ---------------------- */
+#define TWA_PREC_FP64   0   /* FP64 state, FP64 MFMA contraction               */
+#define TWA_PREC_FP32   1   /* FP32 state, FP32 MFMA contraction               */
+#define TWA_PREC_BF16   2   /* FP32 state, BF16 MFMA inputs, FP32 accumulation */
+#define TWA_PREC_FP16   3   /* FP32 state, FP16 MFMA inputs, FP32 accumulation */
+
+/* ---- integrators ------------------------------------------------------ */
+#define TWA_INT_HEUN    0   /* stochastic Heun, Stratonovich reading of Eq. (S1) */
+
+/* ======================================================================
+ * Pump: Eq. (2) and its channel decomposition.
+ * ====================================================================== */
+typedef struct twa_pump twa_pump;   /* opaque, library-owned */
+
+/*
+ * twa_build_pump -- build w_ij = w / (|i-j| + 1)^alpha (Eq. (2), open chain,
+ * i, j = 0..N-1) in FP64 on the device, diagonalise it (the channel rates of
+ * the text after Eq. (2)), and form the noise factor F, the symmetric
+ * positive-semidefinite square root V diag(sqrt(lambda+)) V^T, where lambda+
+ * zeroes eigenvalues below 8 N eps lambda_max (round-off of the rank-one
+ * alpha = 0 case).  F colours the pump noise chi of Eq. (S1):
+ * <chi_i chi_j> = w_ij.
+ *   N      number of atoms, >= 1
+ *   w      pump strength, finite and >= 0
+ *   alpha  exponent, finite and >= 0
+ *   out    host: receives a library-owned handle; release with twa_pump_free.
+ * Errors: TWA_EINVAL (N < 1, w or alpha negative or non-finite, out NULL),
+ *         TWA_ENOMEM, TWA_EHIP, TWA_ENOTPSD.
+ * Uses the current HIP device; blocking.
+ */
+TWA_API int twa_build_pump(int64_t N, double w, double alpha, twa_pump** out);
+
+/*
+ * twa_build_pump_dense -- as twa_build_pump for an arbitrary symmetric PSD
+ * N x N matrix (host, row-major FP64), the generalisation the paper's
+ * Perspectives note allows at unchanged cost.  w and alpha of the handle are
+ * recorded as NaN.  Errors as twa_build_pump; TWA_ENOTPSD if an eigenvalue is
+ * below -1e-10 * lambda_max.
+ */
+TWA_API int twa_build_pump_dense(int64_t N, const double* W_host, twa_pump** out);
+
+/* Releases a handle from twa_build_pump*; NULL is ignored. */
+TWA_API void twa_pump_free(twa_pump* p);
+
+/*
+ * twa_pump_info -- smallest and largest channel rate (eigenvalues of w_ij).
+ * The normalised pump of the paper is w~ = lam_max / (Gamma N); the smallest
+ * rate bounds the relaxation time, tau_r >= 1 / lam_min.  Any output pointer
+ * may be NULL.  Errors: TWA_EINVAL for a NULL handle.
+ */
+TWA_API int twa_pump_info(const twa_pump* p, int64_t* N, double* lam_min, double* lam_max);
+
+/*
+ * twa_pump_copy_matrix -- copies W (which = 0) or F (which = 1) into a host
+ * row-major N x N FP64 buffer.  Errors: TWA_EINVAL, TWA_EHIP.
+ */
+TWA_API int twa_pump_copy_matrix(const twa_pump* p, int which, double* out_host);
+
+/* ======================================================================
+ * Trajectories: Eq. (S1) with discrete initial sampling (SM Sec. S1).
+ * ====================================================================== */
+typedef struct twa_params {
+    const twa_pump* pump;    /* required                                          */
+    double gamma;            /* collective decay rate Gamma (> 0)                  */
+    double s0z;              /* initial s^z of every spin: +1 excited, -1 ground   */
+    int64_t burnin;          /* steps before the averaging window; < 0 = n_steps/2 */
+    int32_t integrator;      /* TWA_INT_HEUN                                       */
+    int32_t precision;       /* TWA_PREC_*                                         */
+    int64_t n_lags;          /* two-time lags L (0 = no two-time correlation)      */
+    int64_t lag_stride;      /* steps per lag; <= 0 = max(1, (n_steps-burnin)/L)   */
+    int32_t point;           /* Philox point index (counter word 3, bits 8..31)    */
+    int32_t tile_config;     /* < 0: automatic (autotuner cache / heuristic)       */
+    void* stream;            /* hipStream_t, NULL = null stream                    */
+    const double* init_state;/* host, optional [3][n_traj][N] (x, y, z planes):    */
+                             /* replaces the discrete sampling when non-NULL       */
+    int32_t timing;          /* 1: HIP events around every contraction launch      */
+                             /* (fills gemm_ms); 0: only the step-loop time        */
+    int32_t use_graph;       /* 1: replay the step loop from captured hipGraphs    */
+    double kappa;            /* weight of the response (commutator) part in the    */
+                             /* two-time correlation; default 1/4                  */
+} twa_params;
+
+/* Fills *p with defaults: gamma 1, s0z +1, burnin -1, Heun, FP32, no lags,
+ * point 0, automatic tiles, null stream, no initial state, no per-launch
+ * timing, hipGraph replay on, kappa 1/4. */
+TWA_API void twa_params_default(twa_params* p);
+
+typedef struct twa_observables {
+    /* ensemble- and time-averaged TWA moments (symmetric order):
+       T2 = <S+S->_TWA = <(S_x^2 + S_y^2)/4>, T3 = <S+ S^z S->_TWA,
+       T4 = <S+S+S-S->_TWA, Z = <S^z>_TWA, ZZ = <S^z S^z>_TWA                */
+    double T2, T3, T4, Z, ZZ;
+    /* normal-ordered observables: Sz = <S^z>; SpSm = T2 + Z/2 (SM step 6);
+       g2 = (T4 + 2 T3 - Z/3 + ZZ/2 - 4 T2/3) / SpSm^2 (Eq. (S2), main text) */
+    double Sz, SpSm, g2;
+    /* delete-one-block jackknife standard errors (32 contiguous blocks of
+       trajectories, fewer if n_traj < 32), same order as above              */
+    double T2_se, T3_se, T4_se, Z_se, ZZ_se, Sz_se, SpSm_se, g2_se;
+    int64_t n_samples;       /* window samples per trajectory                       */
+    int64_t n_lags;          /* lags written                                       */
+    int64_t lag_stride;      /* steps per lag                                      */
+    double max_norm_dev;     /* max over spins of | |s|^2(end) - |s|^2(start) |    */
+    double step_criterion;   /* max(Gamma N, lam_max) dt; the paper asks < 0.05    */
+    int32_t nan_flag;        /* 1 if a NaN/Inf was seen                            */
+    int32_t tile_config;     /* tile configuration used                            */
+    double kernel_ms;        /* device time of the step loop (HIP events)          */
+    double gemm_ms;          /* device time of the contraction launches (events)   */
+    int64_t gemm_launches;   /* number of contraction launches                     */
+    double gemm_flops;       /* algorithmic flops of the contractions              */
+    /* two-time (n_lags > 0): C(l) = Csym(l) + kappa i (chi_xx + chi_yy
+       + i chi_yx - i chi_xy) (Eq. (S3) and the Kubo correction after it);
+       spectrum S(omega) = 2 Re int_0^inf e^{i omega t} C(t) dt (trapezoid on
+       the lag grid, zero padded to 8 L); linewidth = its FWHM (main text)   */
+    double linewidth;        /* FWHM of the spectrum of C                          */
+    double linewidth_sym;    /* FWHM of the spectrum of Csym alone                 */
+} twa_observables;
+
+/* Optional host output buffers of twa_run (any may be NULL). */
+typedef struct twa_outputs {
+    double* corr_blocks;     /* [L][J][2] block sums of the symmetric part
+                                (1/4)(S_x + i S_y)(t0 + l m dt) (S_x - i S_y)(t0) */
+    double* chi_blocks;      /* [L][J][4] block sums of sum_i ds^a_i of the
+                                response copies: xx, yx, xy, yy                   */
+    double* traj_moments;    /* [n_traj][5] per-trajectory window averages of
+                                T2, T3, T4, Z, ZZ                                 */
+    double* final_state;     /* [3][n_traj][N] x, y, z planes at the last step    */
+    int32_t* n_blocks;       /* receives J                                        */
+} twa_outputs;
+
+/*
+ * twa_run -- integrate n_traj independent trajectories of Eq. (S1) for
+ * n_steps steps of size dt and accumulate the observables.
+ *   Noise: Philox4x32-10 keyed by `seed` (counter layout documented with the
+ *   oracle and in the design notes); xi^a dt -> sqrt(Gamma dt) g^a (one
+ *   collective normal pair per trajectory and step), chi^a dt ->
+ *   sqrt(dt) F zeta^a (N normal pairs per trajectory and step).
+ *   Integrator: stochastic Heun (Euler predictor, trapezoidal corrector with
+ *   the same noise increments).
+ *   Window: states after steps burnin+1 .. n_steps are averaged.
+ *   Two-time (n_lags > 0): origin at the state after `burnin` steps; two
+ *   tangent-linear response copies seeded with ds = x^ and ds = y^ on every
+ *   spin (the eps -> 0 limit of the SM's shifted copies) run alongside;
+ *   lag l samples the state after burnin + l * stride steps.
+ *   out   host, required: scalar results.
+ *   outs  host, optional: per-block / per-trajectory arrays.
+ * Errors: TWA_EINVAL (NULL pump/out, n_traj < 1, n_steps < 0, dt <= 0,
+ *         burnin > n_steps, gamma <= 0, unknown precision, lags that do not
+ *         fit: (n_lags - 1) * stride > n_steps - burnin), TWA_ENOMEM,
+ *         TWA_EHIP, TWA_EUNSTABLE.
+ * Deterministic: identical inputs give bitwise identical outputs.
+ */
+TWA_API int twa_run(const twa_params* p, int64_t n_traj, double dt, int64_t n_steps,
+                    uint64_t seed, twa_observables* out, const twa_outputs* outs);
+
+/* ======================================================================
+ * Batched phase-diagram scan: many independent (N, w, alpha) points.
+ * ====================================================================== */
+typedef struct twa_point {
+    int64_t N;
+    double w, alpha;
+    double dt;
+    uint64_t seed;
+} twa_point;
+
+typedef struct twa_batch_opts {
+    int64_t n_traj;          /* trajectories per point                           */
+    int64_t n_steps;         /* steps per point                                  */
+    int64_t burnin;          /* < 0: n_steps / 2                                  */
+    double gamma;
+    double s0z;
+    int32_t precision;       /* TWA_PREC_FP32 / BF16 / FP16                      */
+    int32_t use_graph;       /* capture the step loop in a hipGraph (default 1)  */
+    int32_t steps_per_graph; /* steps captured per graph replay (<= 0: 64)       */
+    const char* tune_cache;  /* autotuner cache file (NULL: no cache)            */
+    void* stream;            /* hipStream_t                                      */
+} twa_batch_opts;
+
+TWA_API void twa_batch_opts_default(twa_batch_opts* o);
+
+/*
+ * twa_run_batch -- runs every point of `pts` (each with its own pump built
+ * internally, Philox point index = position in `pts`) in grouped persistent
+ * launches: every step of every point advances in the same launches, with
+ * the work of all points in one LPT-ordered tile list.  outs[i] receives
+ * point i's observables.  Errors as twa_run.
+ */
+TWA_API int twa_run_batch(const twa_point* pts, int n_points, const twa_batch_opts* o,
+                          twa_observables* outs);
+
+/* ======================================================================
+ * Adjoint: pathwise gradients at fixed noise.
+ * ====================================================================== */
+/*
+ * twa_adjoint -- forward run of twa_run (no two-time) with the state
+ * checkpointed every `ckpt_every` steps, then a reverse sweep through the
+ * Heun steps (each segment recomputed from its checkpoint) giving the
+ * pathwise derivatives, at the fixed Philox stream, of the steady-state
+ * <S+S-> (SpSm) and g2 with respect to w and alpha of an Eq. (2) pump:
+ *   grads[0] = dSpSm/dw, grads[1] = dSpSm/dalpha,
+ *   grads[2] = dg2/dw,   grads[3] = dg2/dalpha.
+ * The observables of the forward run are written to *out.  Requires a pump
+ * from twa_build_pump with w > 0.  Errors as twa_run.
+ */
+TWA_API int twa_adjoint(const twa_params* p, int64_t n_traj, double dt, int64_t n_steps,
+                        uint64_t seed, int32_t ckpt_every, twa_observables* out,
+                        double* grads);
+
+/* ======================================================================
+ * Kernel-level entry points used by the parity tests.
+ * ====================================================================== */
+/*
+ * twa_philox -- raw Philox4x32-10 blocks on the device: for j < n,
+ * out[4j .. 4j+3] = Philox4x32-10(ctr[4j .. 4j+3], key = (key0, key1)).
+ * ctr, out: device, uint32, 4n each.  Errors: TWA_EINVAL, TWA_EHIP.
+ */
+TWA_API int twa_philox(const uint32_t* ctr, int64_t n, uint32_t key0, uint32_t key1,
+                       uint32_t* out, void* stream);
+
+/*
+ * twa_noise -- the Gaussians the step kernels draw for one step: zeta^x,
+ * zeta^y of every (trajectory, spin) and g^x, g^y of every trajectory, in
+ * FP64 (fp64 = 1) or FP32 Box-Muller, written as doubles.
+ *   zeta: device [2][n_traj][N]; g: device [2][n_traj].  Errors as above.
+ */
+TWA_API int twa_noise(uint64_t seed, int64_t step, int32_t point, int64_t n_traj, int64_t N,
+                      int32_t fp64, double* zeta, double* g, void* stream);
+
+/* Last error message of the calling thread ("" if none). */
+TWA_API const char* twa_last_error(void);
+
+/* Library version string. */
+TWA_API const char* twa_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TWA_H */

@@ -1,0 +1,258 @@
+"""MI355X (gfx950) engine for dissipative Truncated-Wigner trajectories.
+
+Thin Python binding of ``libtwa.so`` (C ABI declared in ``include/twa.h``):
+argument marshalling only; every step of the time stepping runs in the
+library's HIP kernels.  PyTorch is used only for device buffers and streams.
+There is no CPU fallback: if the library is missing, importing the binding
+raises, and without a GPU every compute call raises ``TWAError``.
+
+Paper: Chelpanova, Stefanini, O'Keeffe, Marino, "Phase diagram of lasing
+under correlated pump from GPU-accelerated Truncated Wigner dynamics";
+equations of motion Eq. (S1), observables SM Sec. S1 and main text.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtwa.so")
+
+TWA_OK, TWA_EINVAL, TWA_ENOMEM, TWA_EHIP, TWA_ENOTPSD, TWA_EUNSTABLE = 0, -1, -2, -3, -4, -5
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "fp16": 3}
+
+
+class TWAError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("TWA error %d: %s" % (code, msg))
+        self.code = code
+
+
+class _Params(C.Structure):
+    _fields_ = [("pump", C.c_void_p), ("gamma", C.c_double), ("s0z", C.c_double), ("burnin", C.c_int64),
+                ("integrator", C.c_int32), ("precision", C.c_int32), ("n_lags", C.c_int64),
+                ("lag_stride", C.c_int64), ("point", C.c_int32), ("tile_config", C.c_int32),
+                ("stream", C.c_void_p), ("init_state", C.POINTER(C.c_double)), ("timing", C.c_int32),
+                ("use_graph", C.c_int32), ("kappa", C.c_double)]
+
+
+_OBS_DOUBLES1 = ["T2", "T3", "T4", "Z", "ZZ", "Sz", "SpSm", "g2",
+                 "T2_se", "T3_se", "T4_se", "Z_se", "ZZ_se", "Sz_se", "SpSm_se", "g2_se"]
+
+
+class _Obs(C.Structure):
+    _fields_ = ([(n, C.c_double) for n in _OBS_DOUBLES1] +
+                [("n_samples", C.c_int64), ("n_lags", C.c_int64), ("lag_stride", C.c_int64),
+                 ("max_norm_dev", C.c_double), ("step_criterion", C.c_double), ("nan_flag", C.c_int32),
+                 ("tile_config", C.c_int32), ("kernel_ms", C.c_double), ("gemm_ms", C.c_double),
+                 ("gemm_launches", C.c_int64), ("gemm_flops", C.c_double), ("linewidth", C.c_double),
+                 ("linewidth_sym", C.c_double)])
+
+
+class _Outs(C.Structure):
+    _fields_ = [("corr_blocks", C.POINTER(C.c_double)), ("chi_blocks", C.POINTER(C.c_double)),
+                ("traj_moments", C.POINTER(C.c_double)), ("final_state", C.POINTER(C.c_double)),
+                ("n_blocks", C.POINTER(C.c_int32))]
+
+
+class _Point(C.Structure):
+    _fields_ = [("N", C.c_int64), ("w", C.c_double), ("alpha", C.c_double), ("dt", C.c_double),
+                ("seed", C.c_uint64)]
+
+
+class _BatchOpts(C.Structure):
+    _fields_ = [("n_traj", C.c_int64), ("n_steps", C.c_int64), ("burnin", C.c_int64), ("gamma", C.c_double),
+                ("s0z", C.c_double), ("precision", C.c_int32), ("use_graph", C.c_int32),
+                ("steps_per_graph", C.c_int32), ("tune_cache", C.c_char_p), ("stream", C.c_void_p)]
+
+
+def load_library(path: str = LIB_PATH) -> C.CDLL:
+    if not os.path.exists(path):
+        raise ImportError("libtwa.so is not built (run __graft_entry__.build()); no CPU fallback exists")
+    lib = C.CDLL(path)
+    P = C.c_void_p
+    lib.twa_last_error.restype = C.c_char_p
+    lib.twa_version.restype = C.c_char_p
+    lib.twa_build_pump.argtypes = [C.c_int64, C.c_double, C.c_double, C.POINTER(P)]
+    lib.twa_build_pump_dense.argtypes = [C.c_int64, C.POINTER(C.c_double), C.POINTER(P)]
+    lib.twa_pump_free.argtypes = [P]
+    lib.twa_pump_free.restype = None
+    lib.twa_pump_info.argtypes = [P, C.POINTER(C.c_int64), C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    lib.twa_pump_copy_matrix.argtypes = [P, C.c_int, C.POINTER(C.c_double)]
+    lib.twa_params_default.argtypes = [C.POINTER(_Params)]
+    lib.twa_params_default.restype = None
+    lib.twa_run.argtypes = [C.POINTER(_Params), C.c_int64, C.c_double, C.c_int64, C.c_uint64, C.POINTER(_Obs),
+                            C.POINTER(_Outs)]
+    lib.twa_batch_opts_default.argtypes = [C.POINTER(_BatchOpts)]
+    lib.twa_batch_opts_default.restype = None
+    lib.twa_run_batch.argtypes = [C.POINTER(_Point), C.c_int, C.POINTER(_BatchOpts), C.POINTER(_Obs)]
+    lib.twa_adjoint.argtypes = [C.POINTER(_Params), C.c_int64, C.c_double, C.c_int64, C.c_uint64, C.c_int32,
+                                C.POINTER(_Obs), C.POINTER(C.c_double)]
+    lib.twa_philox.argtypes = [P, C.c_int64, C.c_uint32, C.c_uint32, P, P]
+    lib.twa_noise.argtypes = [C.c_uint64, C.c_int64, C.c_int32, C.c_int64, C.c_int64, C.c_int32, P, P, P]
+    for name in ("twa_build_pump", "twa_build_pump_dense", "twa_pump_info", "twa_pump_copy_matrix", "twa_run",
+                 "twa_run_batch", "twa_adjoint", "twa_philox", "twa_noise"):
+        getattr(lib, name).restype = C.c_int
+    return lib
+
+
+_lib = load_library()
+
+
+def _check(rc: int):
+    if rc != TWA_OK:
+        raise TWAError(rc, _lib.twa_last_error().decode())
+
+
+def version() -> str:
+    return _lib.twa_version().decode()
+
+
+def _stream_ptr(stream=None):
+    if stream is not None:
+        return C.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    except Exception:   # pragma: no cover - torch missing
+        pass
+    return C.c_void_p(None)
+
+
+class Pump:
+    """Eq. (2) pump matrix, its channel decomposition and PSD noise factor
+    (library-owned device memory, released on ``close``/garbage collection)."""
+
+    def __init__(self, N: int, w: float = None, alpha: float = None, dense: Optional[np.ndarray] = None):
+        h = C.c_void_p()
+        if dense is not None:
+            W = np.ascontiguousarray(dense, dtype=np.float64)
+            _check(_lib.twa_build_pump_dense(int(N), W.ctypes.data_as(C.POINTER(C.c_double)), C.byref(h)))
+        else:
+            _check(_lib.twa_build_pump(int(N), float(w), float(alpha), C.byref(h)))
+        self._h = h
+        self.N = int(N)
+        self.w = w
+        self.alpha = alpha
+        n, lo, hi = C.c_int64(), C.c_double(), C.c_double()
+        _check(_lib.twa_pump_info(self._h, C.byref(n), C.byref(lo), C.byref(hi)))
+        self.lam_min, self.lam_max = lo.value, hi.value
+
+    @property
+    def handle(self):
+        return self._h
+
+    def matrix(self, which: str = "W") -> np.ndarray:
+        out = np.empty((self.N, self.N))
+        _check(_lib.twa_pump_copy_matrix(self._h, 0 if which == "W" else 1,
+                                         out.ctypes.data_as(C.POINTER(C.c_double))))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.twa_pump_free(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def build_pump(N: int, w: float, alpha: float) -> Pump:
+    return Pump(N, w, alpha)
+
+
+@dataclass
+class RunResult:
+    obs: dict
+    traj_moments: Optional[np.ndarray] = None
+    final_state: Optional[np.ndarray] = None
+    corr_blocks: Optional[np.ndarray] = None
+    chi_blocks: Optional[np.ndarray] = None
+    n_blocks: int = 0
+    status: int = 0
+
+
+def _obs_dict(o: _Obs) -> dict:
+    return {name: getattr(o, name) for name, _ in _Obs._fields_}
+
+
+def run(pump: Pump, n_traj: int, dt: float, n_steps: int, seed: int = 0, *, gamma: float = 1.0,
+        s0z: float = 1.0, burnin: int = -1, precision: str = "fp32", n_lags: int = 0, lag_stride: int = 0,
+        point: int = 0, tile_config: int = -1, init_state: Optional[np.ndarray] = None, timing: bool = False,
+        use_graph: bool = True, kappa: float = 0.25, stream=None, want_traj: bool = False,
+        want_final_state: bool = False, want_lags: bool = False, allow_unstable: bool = False) -> RunResult:
+    """twa_run: n_traj trajectories of Eq. (S1), n_steps Heun steps of size dt."""
+    p = _Params()
+    _lib.twa_params_default(C.byref(p))
+    p.pump = pump.handle
+    p.gamma, p.s0z, p.burnin = gamma, s0z, burnin
+    p.precision = PRECISIONS[precision]
+    p.n_lags, p.lag_stride, p.point, p.tile_config = n_lags, lag_stride, point, tile_config
+    p.stream = _stream_ptr(stream)
+    p.timing = 1 if timing else 0
+    p.use_graph = 1 if use_graph else 0
+    p.kappa = kappa
+    init = None
+    if init_state is not None:
+        init = np.ascontiguousarray(init_state, dtype=np.float64)
+        assert init.shape == (3, n_traj, pump.N)
+        p.init_state = init.ctypes.data_as(C.POINTER(C.c_double))
+    o = _Obs()
+    outs = _Outs()
+    nb = C.c_int32(0)
+    outs.n_blocks = C.pointer(nb)
+    res = RunResult(obs={})
+    J = min(32, n_traj)
+    if want_traj:
+        res.traj_moments = np.zeros((n_traj, 5))
+        outs.traj_moments = res.traj_moments.ctypes.data_as(C.POINTER(C.c_double))
+    if want_final_state:
+        res.final_state = np.zeros((3, n_traj, pump.N))
+        outs.final_state = res.final_state.ctypes.data_as(C.POINTER(C.c_double))
+    if want_lags and n_lags > 0:
+        res.corr_blocks = np.zeros((n_lags, J, 2))
+        res.chi_blocks = np.zeros((n_lags, J, 4))
+        outs.corr_blocks = res.corr_blocks.ctypes.data_as(C.POINTER(C.c_double))
+        outs.chi_blocks = res.chi_blocks.ctypes.data_as(C.POINTER(C.c_double))
+    rc = _lib.twa_run(C.byref(p), int(n_traj), float(dt), int(n_steps), C.c_uint64(seed & (2 ** 64 - 1)),
+                      C.byref(o), C.byref(outs))
+    if not (rc == TWA_EUNSTABLE and allow_unstable):
+        _check(rc)
+    res.status = rc
+    res.obs = _obs_dict(o)
+    res.n_blocks = nb.value
+    return res
+
+
+def philox(ctr: np.ndarray, key0: int, key1: int) -> np.ndarray:
+    """twa_philox on the device: ctr (n, 4) uint32 -> (n, 4) uint32."""
+    import torch
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    n = c.shape[0]
+    dc = torch.from_numpy(c.view(np.int32).copy()).cuda()
+    do = torch.empty_like(dc)
+    _check(_lib.twa_philox(C.c_void_p(dc.data_ptr()), n, key0, key1, C.c_void_p(do.data_ptr()), _stream_ptr()))
+    return do.cpu().numpy().view(np.uint32)
+
+
+def noise(seed: int, step: int, n_traj: int, N: int, point: int = 0, fp64: bool = True):
+    """twa_noise: the step's Gaussians (zeta^x, zeta^y of shape (n_traj, N); g^x, g^y)."""
+    import torch
+    z = torch.empty((2, n_traj, N), dtype=torch.float64, device="cuda")
+    g = torch.empty((2, n_traj), dtype=torch.float64, device="cuda")
+    _check(_lib.twa_noise(C.c_uint64(seed), step, point, n_traj, N, 1 if fp64 else 0, C.c_void_p(z.data_ptr()),
+                          C.c_void_p(g.data_ptr()), _stream_ptr()))
+    z = z.cpu().numpy()
+    g = g.cpu().numpy()
+    return (z[0], z[1]), (g[0], g[1])
+
+
+__all__ = ["Pump", "build_pump", "run", "philox", "noise", "TWAError", "version", "PRECISIONS", "LIB_PATH"]

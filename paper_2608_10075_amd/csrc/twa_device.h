@@ -1,0 +1,151 @@
+// Device-side building blocks: counter-based noise, number formats of the
+// contraction, and the MFMA fragments used by the step kernels (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/twa.h"
+
+namespace twa {
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two 32x32
+// -> 64-bit multiplies with the published multipliers, the key advanced by
+// the published Weyl increments between rounds.
+struct U4 {
+    uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c.x), lo0 = 0xD2511F53u * c.x;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z), lo1 = 0xCD9E8D57u * c.z;
+        c = U4{hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0};
+    }
+    return c;
+}
+
+// Counter words: (slot, trajectory, step, tag | point << 8).
+enum : uint32_t { TAG_PUMP = 0u, TAG_COLLECTIVE = 1u, TAG_INIT = 2u };
+
+// Box-Muller (Box & Muller 1958) on two words.  u1 = ((a >> 8) + 1) 2^-24 in
+// (0, 1] and u2 = (b >> 8) 2^-24 are exact in binary32.
+__device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, float& z0, float& z1) {
+    const float u1 = (float)((a >> 8) + 1u) * 5.9604644775390625e-08f;
+    const float u2 = (float)(b >> 8) * 5.9604644775390625e-08f;
+    const float r = sqrtf(-2.0f * logf(u1));
+    float s, c;
+    sincospif(2.0f * u2, &s, &c);
+    z0 = r * c;
+    z1 = r * s;
+}
+__device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, double& z0, double& z1) {
+    const double u1 = (double)((a >> 8) + 1u) * 5.9604644775390625e-08;
+    const double u2 = (double)(b >> 8) * 5.9604644775390625e-08;
+    const double r = sqrt(-2.0 * log(u1));
+    double s, c;
+    sincospi(2.0 * u2, &s, &c);
+    z0 = r * c;
+    z1 = r * s;
+}
+
+// Operand column of component a (0 = x, 1 = y) of trajectory k: x and y of
+// 16 consecutive trajectories sit in two adjacent 16-column blocks, so one
+// lane of an MFMA output pair holds both components of one (spin, trajectory).
+__device__ __forceinline__ int64_t opcol(int64_t k, int a) {
+    return 32 * (k >> 4) + 16 * a + (k & 15);
+}
+
+// ---------------------------------------------------------------------------
+// number formats
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+struct bf16s {
+    uint16_t v;
+};
+
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+union Frag16 {
+    uint4 u;
+    double d[2];
+    float f[4];
+    bf16x8 b;
+    f16x8 h;
+};
+
+template <int PREC>
+struct Prec;
+
+template <>
+struct Prec<TWA_PREC_FP64> {
+    typedef double G;   // contraction operand
+    typedef double S;   // state / accumulator
+    typedef f64x4 AV;
+    __device__ static __forceinline__ G to_g(S v) { return v; }
+    __device__ static __forceinline__ void mma(AV& c, const uint4& a, const uint4& b) {
+        Frag16 fa, fb;
+        fa.u = a;
+        fb.u = b;
+        c = __builtin_amdgcn_mfma_f64_16x16x4f64(fa.d[0], fb.d[0], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f64_16x16x4f64(fa.d[1], fb.d[1], c, 0, 0, 0);
+    }
+};
+
+template <>
+struct Prec<TWA_PREC_FP32> {
+    typedef float G;
+    typedef float S;
+    typedef f32x4 AV;
+    __device__ static __forceinline__ G to_g(S v) { return v; }
+    __device__ static __forceinline__ void mma(AV& c, const uint4& a, const uint4& b) {
+        Frag16 fa, fb;
+        fa.u = a;
+        fb.u = b;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) c = __builtin_amdgcn_mfma_f32_16x16x4f32(fa.f[j], fb.f[j], c, 0, 0, 0);
+    }
+};
+
+template <>
+struct Prec<TWA_PREC_BF16> {
+    typedef bf16s G;
+    typedef float S;
+    typedef f32x4 AV;
+    __device__ static __forceinline__ G to_g(S v) { return G{f32_to_bf16_rne(v)}; }
+    __device__ static __forceinline__ void mma(AV& c, const uint4& a, const uint4& b) {
+        Frag16 fa, fb;
+        fa.u = a;
+        fb.u = b;
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa.b, fb.b, c, 0, 0, 0);
+    }
+};
+
+template <>
+struct Prec<TWA_PREC_FP16> {
+    typedef _Float16 G;
+    typedef float S;
+    typedef f32x4 AV;
+    __device__ static __forceinline__ G to_g(S v) { return (_Float16)v; }
+    __device__ static __forceinline__ void mma(AV& c, const uint4& a, const uint4& b) {
+        Frag16 fa, fb;
+        fa.u = a;
+        fb.u = b;
+        c = __builtin_amdgcn_mfma_f32_16x16x32_f16(fa.h, fb.h, c, 0, 0, 0);
+    }
+};
+
+}  // namespace twa

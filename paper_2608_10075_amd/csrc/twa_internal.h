@@ -1,0 +1,123 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+#include <string>
+
+#include "../../include/twa.h"
+
+namespace twa {
+
+// ---------------------------------------------------------------------------
+// error plumbing
+void set_error(const std::string& msg);
+struct Status {
+    int code = TWA_OK;
+    std::string msg;
+};
+#define TWA_HIP_CHECK(expr)                                                       \
+    do {                                                                          \
+        hipError_t _e = (expr);                                                   \
+        if (_e != hipSuccess) {                                                   \
+            ::twa::set_error(std::string(#expr) + ": " + hipGetErrorString(_e));  \
+            return TWA_EHIP;                                                      \
+        }                                                                         \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// tile configurations of the channel-mixing contraction.  A configuration is
+// (MT rows of spins, NT operand columns = NT/2 trajectories x 2 components,
+// K bytes per LDS stage, waves along M, waves along N).
+struct TileCfg {
+    int id;
+    int mt, nt, kbytes, waves_m, waves_n;
+    const char* name;
+};
+int n_tile_cfgs();
+const TileCfg& tile_cfg(int id);
+int pick_tile_cfg(int precision, int64_t N, int64_t n_traj);
+
+inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+int gemm_elt_bytes(int precision);
+int state_elt_bytes(int precision);
+
+// ---------------------------------------------------------------------------
+// device buffers and launch geometry of one trajectory ensemble
+struct Geometry {
+    int precision;
+    int cfg;
+    int64_t N, B;        // atoms, trajectories
+    int64_t P, Bp;       // padded
+    int64_t nmt;         // P / MT
+    int64_t C2;          // 2 * Bp operand columns
+    int64_t kt;          // K elements per LDS stage
+};
+
+struct EnsembleBuffers {
+    void* A = nullptr;          // GT [P][2P]  = [-dt/2 W | -sqrt(dt) F]
+    void* Xop = nullptr;        // GT [C2][2P] rows: (s^a | zeta^a) of one column
+    void* Dop = nullptr;        // GT [C2][P]  predictor increments
+    void* s[2] = {nullptr, nullptr};   // ST [3][Bp][P] ping-pong state
+    void* dlt = nullptr;        // ST [3][Bp][P] predictor increment
+    void* Y = nullptr;          // ST [2][Bp][P] contraction output of stage 1 (and 2)
+    void* part[2] = {nullptr, nullptr};// ST [3][nmt][Bp] partial spin sums: [0] current state, [1] predictor
+    void* g = nullptr;          // ST [2][Bp] collective normals of the step
+    void* norm0 = nullptr;      // ST [Bp][P]
+    void* mom = nullptr;        // ST [5][2][Bp] Kahan (sum, compensation)
+    // response copies (two-time)
+    void* tXop = nullptr;       // GT [2][C2][P]
+    void* tDop = nullptr;       // GT [2][C2][P]
+    void* ts[2] = {nullptr, nullptr};  // ST [2][3][Bp][P]
+    void* tdlt = nullptr;       // ST [2][3][Bp][P]
+    void* tY = nullptr;         // ST [2][2][Bp][P]
+    void* tpart[2] = {nullptr, nullptr};// ST [2][3][nmt][Bp]
+    void* sm0 = nullptr;        // ST [2][Bp]
+    double* lag = nullptr;      // [L][J][6]
+    int64_t* step = nullptr;    // device step counter
+    float* diag = nullptr;      // per-block max norm deviation / nan flags
+};
+
+struct StepConsts {
+    double c1;      // Gamma dt / 2
+    double c2;      // sqrt(Gamma dt)
+    double s0z;
+    uint32_t key0, key1;
+    int32_t point;
+    int64_t burnin, lag_stride, n_lags;
+    int J;
+};
+
+// kernel launchers (twa_kernels.hip)
+int launch_build_A(const Geometry& g, const double* W, const double* F, double dt, void* A, hipStream_t st);
+int launch_init_state(const Geometry& g, const EnsembleBuffers& b, const StepConsts& c,
+                      const double* init_dev, hipStream_t st);
+int launch_reduce_state(const Geometry& g, const void* s, void* part, hipStream_t st);
+int launch_noise(const Geometry& g, const EnsembleBuffers& b, const StepConsts& c, hipStream_t st);
+int launch_gemm(const Geometry& g, const EnsembleBuffers& b, const StepConsts& c, int stage,
+                bool tangent, int cur, bool store_y2, hipStream_t st);
+int launch_seed_tangents(const Geometry& g, const EnsembleBuffers& b, int cur, hipStream_t st);
+int launch_observe(const Geometry& g, const EnsembleBuffers& b, const StepConsts& c, int cur,
+                   bool tangents, hipStream_t st);
+int launch_finish(const Geometry& g, const EnsembleBuffers& b, int cur, int nblk, hipStream_t st);
+int launch_export_state(const Geometry& g, const void* s, double* out_dev, hipStream_t st);
+int launch_advance_step(int64_t* step, hipStream_t st);
+int launch_philox(const uint32_t* ctr, int64_t n, uint32_t k0, uint32_t k1, uint32_t* out, hipStream_t st);
+int launch_noise_debug(uint64_t seed, int64_t step, int32_t point, int64_t B, int64_t N, int fp64,
+                       double* zeta, double* g, hipStream_t st);
+
+// pump (twa_pump.hip)
+}  // namespace twa
+
+struct twa_pump {
+    int64_t N;
+    double w, alpha;
+    double lam_min, lam_max;
+    double* W = nullptr;     // device FP64 [N][N]
+    double* F = nullptr;     // device FP64 [N][N]
+    double* V = nullptr;     // device FP64 eigenvectors, column-major (column j = vector j)
+    double* lam = nullptr;   // host eigenvalues ascending [N]
+    int device = 0;
+};

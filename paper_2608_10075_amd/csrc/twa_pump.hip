@@ -1,0 +1,250 @@
+// Pump matrix of Eq. (2), its channel decomposition (eigenvalues of w_ij, text
+// after Eq. (2)) and the PSD square-root noise factor, all FP64 on the device.
+// The eigendecomposition is a one-time setup step done with rocSOLVER's
+// divide-and-conquer symmetric eigensolver; F = (V diag(sqrt(lambda+)))
+// (V diag(sqrt(lambda+)))^T with rocBLAS dgemm.
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <cfloat>
+#include <cmath>
+#include <vector>
+
+#include "twa_internal.h"
+
+namespace twa {
+
+__global__ void pump_matrix_kernel(int64_t N, double w, double alpha, double* W) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= N * N) return;
+    const int64_t i = t / N, j = t % N;
+    const double d = (double)(i > j ? i - j : j - i);
+    W[t] = w / pow(d + 1.0, alpha);
+}
+
+__global__ void scale_columns_kernel(int64_t N, const double* V, const double* r, double* Vs) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= N * N) return;
+    const int64_t col = t / N;   // column-major
+    Vs[t] = V[t] * r[col];
+}
+
+__global__ void symmetrize_kernel(int64_t N, double* F) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= N * N) return;
+    const int64_t i = t / N, j = t % N;
+    if (j <= i) return;
+    const double v = 0.5 * (F[i * N + j] + F[j * N + i]);
+    F[i * N + j] = v;
+    F[j * N + i] = v;
+}
+
+static int factorise(twa_pump* p) {
+    const int64_t N = p->N;
+    if (N > 46340) {
+        set_error("N too large for a dense FP64 factorisation on one device");
+        return TWA_EINVAL;
+    }
+    const size_t bytes = (size_t)N * N * sizeof(double);
+    double *D = nullptr, *E = nullptr, *r = nullptr, *Vs = nullptr;
+    rocblas_int* info = nullptr;
+    rocblas_handle h = nullptr;
+    int rc = TWA_OK;
+    auto fail = [&](int code, const std::string& m) {
+        set_error(m);
+        rc = code;
+    };
+    std::vector<double> lam((size_t)N), rr((size_t)N);
+    if (hipMalloc(&p->V, bytes) != hipSuccess || hipMalloc(&D, N * sizeof(double)) != hipSuccess ||
+        hipMalloc(&E, N * sizeof(double)) != hipSuccess || hipMalloc(&r, N * sizeof(double)) != hipSuccess ||
+        hipMalloc(&Vs, bytes) != hipSuccess || hipMalloc(&info, sizeof(rocblas_int)) != hipSuccess ||
+        hipMalloc(&p->F, bytes) != hipSuccess) {
+        fail(TWA_ENOMEM, "device allocation for the pump factorisation failed");
+        goto done;
+    }
+    if (rocblas_create_handle(&h) != rocblas_status_success) {
+        fail(TWA_EHIP, "rocblas_create_handle failed");
+        goto done;
+    }
+    if (hipMemcpy(p->V, p->W, bytes, hipMemcpyDeviceToDevice) != hipSuccess) {
+        fail(TWA_EHIP, "hipMemcpy failed");
+        goto done;
+    }
+    // symmetric matrix: row- and column-major storage coincide
+    if (rocsolver_dsyevd(h, rocblas_evect_original, rocblas_fill_upper, (rocblas_int)N, p->V, (rocblas_int)N, D, E,
+                         info) != rocblas_status_success) {
+        fail(TWA_EHIP, "rocsolver_dsyevd failed");
+        goto done;
+    }
+    {
+        rocblas_int hinfo = 0;
+        if (hipMemcpy(&hinfo, info, sizeof(hinfo), hipMemcpyDeviceToHost) != hipSuccess ||
+            hipMemcpy(lam.data(), D, N * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) {
+            fail(TWA_EHIP, "hipMemcpy failed");
+            goto done;
+        }
+        if (hinfo != 0) {
+            fail(TWA_EHIP, "rocsolver_dsyevd did not converge");
+            goto done;
+        }
+    }
+    p->lam_min = lam[0];
+    p->lam_max = lam[(size_t)N - 1];
+    if (p->lam_min < -1e-10 * std::fabs(p->lam_max)) {
+        fail(TWA_ENOTPSD, "pump matrix is not positive semidefinite");
+        goto done;
+    }
+    {
+        // eigenvalues within round-off of zero (rank-one alpha = 0) count as zero
+        const double tol = 8.0 * (double)N * DBL_EPSILON * std::max(p->lam_max, 0.0);
+        for (int64_t j = 0; j < N; ++j) rr[(size_t)j] = lam[(size_t)j] > tol ? std::sqrt(lam[(size_t)j]) : 0.0;
+    }
+    p->lam = (double*)malloc(N * sizeof(double));
+    if (!p->lam) {
+        fail(TWA_ENOMEM, "host allocation failed");
+        goto done;
+    }
+    for (int64_t j = 0; j < N; ++j) p->lam[j] = lam[(size_t)j];
+    if (hipMemcpy(r, rr.data(), N * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+        fail(TWA_EHIP, "hipMemcpy failed");
+        goto done;
+    }
+    {
+        const int64_t n2 = N * N;
+        hipLaunchKernelGGL(scale_columns_kernel, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, 0, N, p->V, r, Vs);
+        const double one = 1.0, zero = 0.0;
+        // column-major F = Vs Vs^T
+        if (rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_transpose, (rocblas_int)N, (rocblas_int)N,
+                          (rocblas_int)N, &one, Vs, (rocblas_int)N, Vs, (rocblas_int)N, &zero, p->F,
+                          (rocblas_int)N) != rocblas_status_success) {
+            fail(TWA_EHIP, "rocblas_dgemm failed");
+            goto done;
+        }
+        hipLaunchKernelGGL(symmetrize_kernel, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, 0, N, p->F);
+        if (hipDeviceSynchronize() != hipSuccess) {
+            fail(TWA_EHIP, "pump factorisation kernels failed");
+            goto done;
+        }
+    }
+done:
+    if (h) rocblas_destroy_handle(h);
+    hipFree(D);
+    hipFree(E);
+    hipFree(r);
+    hipFree(Vs);
+    hipFree(info);
+    return rc;
+}
+
+static void pump_release(twa_pump* p) {
+    if (!p) return;
+    hipFree(p->W);
+    hipFree(p->F);
+    hipFree(p->V);
+    free(p->lam);
+    delete p;
+}
+
+}  // namespace twa
+
+extern "C" {
+
+TWA_API int twa_build_pump(int64_t N, double w, double alpha, twa_pump** out) {
+    using namespace twa;
+    if (!out || N < 1 || !std::isfinite(w) || !std::isfinite(alpha) || w < 0 || alpha < 0) {
+        set_error("twa_build_pump: need N >= 1, finite w >= 0, finite alpha >= 0 and an output pointer");
+        return TWA_EINVAL;
+    }
+    *out = nullptr;
+    twa_pump* p = new twa_pump();
+    p->N = N;
+    p->w = w;
+    p->alpha = alpha;
+    hipGetDevice(&p->device);
+    if (hipMalloc(&p->W, (size_t)N * N * sizeof(double)) != hipSuccess) {
+        delete p;
+        set_error("twa_build_pump: device allocation failed");
+        return TWA_ENOMEM;
+    }
+    const int64_t n2 = N * N;
+    hipLaunchKernelGGL(pump_matrix_kernel, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, 0, N, w, alpha, p->W);
+    if (hipGetLastError() != hipSuccess) {
+        pump_release(p);
+        set_error("twa_build_pump: kernel launch failed");
+        return TWA_EHIP;
+    }
+    int rc = factorise(p);
+    if (rc) {
+        pump_release(p);
+        return rc;
+    }
+    *out = p;
+    return TWA_OK;
+}
+
+TWA_API int twa_build_pump_dense(int64_t N, const double* W_host, twa_pump** out) {
+    using namespace twa;
+    if (!out || N < 1 || !W_host) {
+        set_error("twa_build_pump_dense: need N >= 1, a matrix and an output pointer");
+        return TWA_EINVAL;
+    }
+    for (int64_t i = 0; i < N; ++i)
+        for (int64_t j = 0; j < N; ++j) {
+            const double a = W_host[i * N + j], b = W_host[j * N + i];
+            if (!std::isfinite(a) || std::fabs(a - b) > 1e-12 * (std::fabs(a) + std::fabs(b))) {
+                set_error("twa_build_pump_dense: matrix must be finite and symmetric");
+                return TWA_EINVAL;
+            }
+        }
+    *out = nullptr;
+    twa_pump* p = new twa_pump();
+    p->N = N;
+    p->w = NAN;
+    p->alpha = NAN;
+    hipGetDevice(&p->device);
+    if (hipMalloc(&p->W, (size_t)N * N * sizeof(double)) != hipSuccess) {
+        delete p;
+        set_error("twa_build_pump_dense: device allocation failed");
+        return TWA_ENOMEM;
+    }
+    if (hipMemcpy(p->W, W_host, (size_t)N * N * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+        pump_release(p);
+        set_error("twa_build_pump_dense: hipMemcpy failed");
+        return TWA_EHIP;
+    }
+    int rc = factorise(p);
+    if (rc) {
+        pump_release(p);
+        return rc;
+    }
+    *out = p;
+    return TWA_OK;
+}
+
+TWA_API void twa_pump_free(twa_pump* p) { twa::pump_release(p); }
+
+TWA_API int twa_pump_info(const twa_pump* p, int64_t* N, double* lam_min, double* lam_max) {
+    if (!p) {
+        twa::set_error("twa_pump_info: NULL handle");
+        return TWA_EINVAL;
+    }
+    if (N) *N = p->N;
+    if (lam_min) *lam_min = p->lam_min;
+    if (lam_max) *lam_max = p->lam_max;
+    return TWA_OK;
+}
+
+TWA_API int twa_pump_copy_matrix(const twa_pump* p, int which, double* out_host) {
+    if (!p || !out_host || (which != 0 && which != 1)) {
+        twa::set_error("twa_pump_copy_matrix: bad arguments");
+        return TWA_EINVAL;
+    }
+    const double* src = which == 0 ? p->W : p->F;
+    if (hipMemcpy(out_host, src, (size_t)p->N * p->N * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) {
+        twa::set_error("twa_pump_copy_matrix: hipMemcpy failed");
+        return TWA_EHIP;
+    }
+    return TWA_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,69 @@
+// Run-driver internals shared by the single-run, batched and adjoint paths.
+#pragma once
+
+#include <complex>
+#include <vector>
+
+#include "twa_internal.h"
+
+namespace twa {
+
+// HIP-event timing of the contraction launches, harvested in batches so that
+// the number of live events stays bounded.
+struct StepTimer {
+    static constexpr int POOL = 256;
+    std::vector<hipEvent_t> ev;
+    int used = 0;
+    bool open = false;
+    double total_ms = 0.0;
+    int64_t count = 0;
+    int init() {
+        ev.resize(2 * POOL);
+        for (auto& e : ev)
+            if (hipEventCreate(&e) != hipSuccess) return TWA_EHIP;
+        return TWA_OK;
+    }
+    void begin(hipStream_t st) {
+        if (used == POOL) harvest(st);
+        hipEventRecord(ev[2 * used], st);
+        open = true;
+    }
+    void end(hipStream_t st) {
+        if (!open) return;
+        hipEventRecord(ev[2 * used + 1], st);
+        ++used;
+        open = false;
+    }
+    void harvest(hipStream_t st) {
+        hipStreamSynchronize(st);
+        for (int i = 0; i < used; ++i) {
+            float ms = 0.f;
+            hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]);
+            total_ms += ms;
+            ++count;
+        }
+        used = 0;
+    }
+    ~StepTimer() {
+        for (auto& e : ev)
+            if (e) hipEventDestroy(e);
+    }
+};
+
+void free_buffers(EnsembleBuffers& b);
+int alloc_buffers(const Geometry& g, bool tangents, int64_t L, int J, EnsembleBuffers& b);
+Geometry make_geometry(int precision, int cfg, int64_t N, int64_t B);
+void finalize_moments(const std::vector<double>& traj, int64_t B, twa_observables* o);
+double linewidth_of(const std::vector<std::complex<double>>& corr, double tau);
+
+// per-launch timers for the two contraction stages (primal)
+struct GemmTimers {
+    StepTimer s1, s2;
+};
+
+int launch_step_kernels(const Geometry& g, EnsembleBuffers& b, const StepConsts& c, int cur, bool tan_active,
+                        GemmTimers* tm, hipStream_t st);
+int run_single(const twa_params* p, int64_t n_traj, double dt, int64_t n_steps, uint64_t seed,
+               twa_observables* out, const twa_outputs* outs);
+
+}  // namespace twa
