@@ -95,6 +95,10 @@ struct Prec<TWA_PREC_FP64> {
     typedef double G;   // contraction operand
     typedef double S;   // state / accumulator
     typedef f64x4 AV;
+    // The f64 16x16x4 MFMA returns row (lane/16) + 4 r in register r; feeding
+    // A-operand row m with spin 4 (m % 4) + m / 4 makes register r of lane l
+    // hold spin 4 (l/16) + r, the layout of the other formats.
+    __device__ static __forceinline__ int arow(int m) { return 4 * (m & 3) + (m >> 2); }
     __device__ static __forceinline__ G to_g(S v) { return v; }
     __device__ static __forceinline__ void mma(AV& c, const uint4& a, const uint4& b) {
         Frag16 fa, fb;
@@ -107,6 +111,8 @@ struct Prec<TWA_PREC_FP64> {
 
 template <>
 struct Prec<TWA_PREC_FP32> {
+    // 16x16 MFMA output: register r of lane l holds row 4 (l/16) + r
+    __device__ static __forceinline__ int arow(int m) { return m; }
     typedef float G;
     typedef float S;
     typedef f32x4 AV;
@@ -122,6 +128,8 @@ struct Prec<TWA_PREC_FP32> {
 
 template <>
 struct Prec<TWA_PREC_BF16> {
+    // 16x16 MFMA output: register r of lane l holds row 4 (l/16) + r
+    __device__ static __forceinline__ int arow(int m) { return m; }
     typedef bf16s G;
     typedef float S;
     typedef f32x4 AV;
@@ -136,6 +144,8 @@ struct Prec<TWA_PREC_BF16> {
 
 template <>
 struct Prec<TWA_PREC_FP16> {
+    // 16x16 MFMA output: register r of lane l holds row 4 (l/16) + r
+    __device__ static __forceinline__ int arow(int m) { return m; }
     typedef _Float16 G;
     typedef float S;
     typedef f32x4 AV;

@@ -1,8 +1,8 @@
 // Pump matrix of Eq. (2), its channel decomposition (eigenvalues of w_ij, text
 // after Eq. (2)) and the PSD square-root noise factor, all FP64 on the device.
 // The eigendecomposition is a one-time setup step done with rocSOLVER's
-// divide-and-conquer symmetric eigensolver; F = (V diag(sqrt(lambda+)))
-// (V diag(sqrt(lambda+)))^T with rocBLAS dgemm.
+// divide-and-conquer symmetric eigensolver; F = (V diag(sqrt(lambda+))) V^T
+// with rocBLAS dgemm.
 #include <rocblas/rocblas.h>
 #include <rocsolver/rocsolver.h>
 
@@ -113,9 +113,9 @@ static int factorise(twa_pump* p) {
         const int64_t n2 = N * N;
         hipLaunchKernelGGL(scale_columns_kernel, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, 0, N, p->V, r, Vs);
         const double one = 1.0, zero = 0.0;
-        // column-major F = Vs Vs^T
+        // column-major F = (V diag(sqrt(lambda+))) V^T
         if (rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_transpose, (rocblas_int)N, (rocblas_int)N,
-                          (rocblas_int)N, &one, Vs, (rocblas_int)N, Vs, (rocblas_int)N, &zero, p->F,
+                          (rocblas_int)N, &one, Vs, (rocblas_int)N, p->V, (rocblas_int)N, &zero, p->F,
                           (rocblas_int)N) != rocblas_status_success) {
             fail(TWA_EHIP, "rocblas_dgemm failed");
             goto done;

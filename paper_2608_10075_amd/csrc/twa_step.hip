@@ -196,7 +196,7 @@ __global__ __launch_bounds__(64 * WMW * WNW) void heun_stage_kernel(GemmArgs<PRE
             const int off = seg * 64 + (lane >> 4) * 16;
 #pragma unroll
             for (int i = 0; i < BI; ++i)
-                af[i] = *reinterpret_cast<const uint4*>(base + (wm0 + 16 * i + (lane & 15)) * RS + off);
+                af[i] = *reinterpret_cast<const uint4*>(base + (wm0 + 16 * i + Prec<PREC>::arow(lane & 15)) * RS + off);
 #pragma unroll
             for (int j = 0; j < BJ; ++j)
                 xf[j] = *reinterpret_cast<const uint4*>(base + (MT + wn0 + 16 * j + (lane & 15)) * RS + off);
