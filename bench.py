@@ -1,0 +1,184 @@
+#!/usr/bin/env python3
+"""Throughput of the TWA trajectory hot path on one MI355X.
+
+Workload (the headline configuration): a chain of N = 10^4 atoms, pump
+exponent alpha = 1, w = ln(N) Gamma, Gamma = 1, 1024 trajectories, dt = 1e-4,
+2e4 stochastic Heun steps of Eq. (S1) with the averaging window over the last
+half, the channel-mixing contraction in BF16 on MFMA with FP32 accumulation
+and FP32 spin updates.  All inputs are synthetic: the Philox stream of the
+method, keyed by seed 0.
+
+One bench "step" is one complete ``twa_run`` of that workload (noise,
+contractions, Heun stages, observables); the pump factorisation is built once
+before the timed region and reported separately.  ``value`` is
+trajectory-atom-steps/s = n_traj * N * n_steps / wall time per run.
+
+The ``roofline`` object refers to the predictor contraction (the larger of the
+two contraction launches of a step): algorithmic flops per launch
+2 * N * (2N) * (2 n_traj), divided by its mean launch duration from HIP events
+recorded by the library on its stream during the timed runs.
+
+``cpu_baseline`` times the FP64 NumPy oracle (test infrastructure) on the
+host's cores on a bounded sample of the same workload (a few trajectories for
+a few steps at N = 10^4).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "trajectory-atom-steps/s at N=1e4 + adjoint d(g2)/d(w,alpha) cost vs forward"
+PEAK_TFLOPS = {"bf16": 2500.0, "fp16": 2500.0, "fp32": 157.3, "fp64": 78.6}
+KERNEL_SOURCES = ["paper_2608_10075_amd/csrc/twa_step.hip", "paper_2608_10075_amd/csrc/twa_device.h"]
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(workload: str, precision: str):
+    """HBM bytes per launch of the predictor contraction from the committed
+    rocprofv3 counter summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "stage1_traffic_%s_%s.json" % (workload, precision))
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except Exception:
+        return None
+    if d.get("source_sha") != kernel_source_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def cpu_baseline(N, w, alpha, dt, budget_s=15.0):
+    """The FP64 oracle as it stands, timed on a bounded sample of the workload."""
+    import numpy as np
+    from oracle import pump as opump, twa as otwa
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    t0 = time.time()
+    p = opump.build_pump(N, w, alpha)
+    build_s = time.time() - t0
+    B = 4
+    cfg = otwa.RunConfig(n_spin=N, w=w, alpha=alpha, n_traj=B, dt=dt, n_steps=1, seed=0)
+    state = otwa.initial_state(0, B, N)
+    t0 = time.time()
+    state = otwa.run_steps(state, p, cfg, 0, 2)
+    per = (time.time() - t0) / 2
+    steps = max(2, int(budget_s / max(per, 1e-6)))
+    t0 = time.time()
+    otwa.run_steps(state, p, cfg, 2, steps)
+    el = time.time() - t0
+    return {"value": B * N * steps / el, "unit": "trajectory-atom-steps/s", "cores": int(cores),
+            "kind": "oracle",
+            "sample": "FP64 NumPy oracle, N=%d, %d trajectories x %d Heun steps (%.1f s); pump eigendecomposition "
+                      "%.1f s not included" % (N, B, steps, el, build_s)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", default="bf16", choices=sorted(PEAK_TFLOPS))
+    ap.add_argument("--tile-config", type=int, default=-1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (trajectories would shard "
+              "across GPUs with one all-reduce of the accumulators at the end)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    torch.cuda.set_device(0)
+    import paper_2608_10075_amd as twa
+
+    N, alpha, B, dt, T = 10000, 1.0, 1024, 1e-4, 20000
+    w = math.log(N)
+    prec = args.precision
+    workload = "n1e4"
+    print("[bench] building pump N=%d alpha=%g w=%.4f" % (N, alpha, w), file=sys.stderr, flush=True)
+    t0 = time.time()
+    pump = twa.build_pump(N, w, alpha)
+    torch.cuda.synchronize()
+    pump_s = time.time() - t0
+
+    def one(timing):
+        return twa.run(pump, B, dt, T, seed=0, precision=prec, tile_config=args.tile_config, timing=timing)
+
+    for i in range(args.warmup):
+        print("[bench] warmup run %d/%d" % (i + 1, args.warmup), file=sys.stderr, flush=True)
+        one(True)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    results = []
+    for i in range(args.steps):
+        print("[bench] timed run %d/%d" % (i + 1, args.steps), file=sys.stderr, flush=True)
+        results.append(one(True))
+    torch.cuda.synchronize()
+    wall = time.time() - t0
+    ms_per_step = 1e3 * wall / args.steps
+    value = B * N * T * args.steps / wall
+
+    s1_ms = sum(r.obs["stage1_ms"] for r in results)
+    s1_n = sum(r.obs["stage1_launches"] for r in results)
+    s2_ms = sum(r.obs["stage2_ms"] for r in results)
+    s2_n = sum(r.obs["stage2_launches"] for r in results)
+    flops1 = 2.0 * N * (2 * N) * (2 * B)
+    flops2 = 2.0 * N * N * (2 * B)
+    ach1 = flops1 / (s1_ms / s1_n * 1e-3) / 1e12
+    ach2 = flops2 / (s2_ms / s2_n * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[prec]
+    obs = results[-1].obs
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "trajectory-atom-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": prec,
+        "data": "synthetic",
+        "config": {"workload": "TWA chain N=10000 alpha=1 w=ln(N) Gamma=1, 1024 trajectories, dt=1e-4, %d Heun "
+                               "steps, window = last half, %s channel-mixing contraction" % (T, prec),
+                   "N": N, "alpha": alpha, "w": w, "n_traj": B, "dt": dt, "n_steps": T, "precision": prec,
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "mfma", "achieved": ach1, "peak": peak, "unit": "TFLOP/s", "frac": ach1 / peak,
+                     "traffic": traffic_from_profiles(workload, prec),
+                     "kernel": "heun_stage_kernel stage 1 (predictor contraction, K = 2N)",
+                     "flops_per_launch": flops1, "mean_launch_ms": s1_ms / s1_n},
+        "roofline_stage2": {"achieved": ach2, "peak": peak, "unit": "TFLOP/s", "frac": ach2 / peak,
+                            "mean_launch_ms": s2_ms / s2_n, "flops_per_launch": flops2},
+        "pump_build_s": pump_s,
+        "observables": {k: obs[k] for k in ("Sz", "SpSm", "g2", "Sz_se", "SpSm_se", "g2_se", "max_norm_dev",
+                                             "step_criterion")},
+        "tile_config": obs["tile_config"],
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(N, w, alpha, dt)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -128,7 +128,7 @@ typedef struct twa_params {
     const double* init_state;/* host, optional [3][n_traj][N] (x, y, z planes):    */
                              /* replaces the discrete sampling when non-NULL       */
     int32_t timing;          /* 1: HIP events around every contraction launch      */
-                             /* (fills gemm_ms); 0: only the step-loop time        */
+                             /* (fills stage*_ms); 0: only the step-loop time     */
     int32_t use_graph;       /* 1: replay the step loop from captured hipGraphs    */
     double kappa;            /* weight of the response (commutator) part in the    */
                              /* two-time correlation; default 1/4                  */
@@ -158,9 +158,11 @@ typedef struct twa_observables {
     int32_t nan_flag;        /* 1 if a NaN/Inf was seen                            */
     int32_t tile_config;     /* tile configuration used                            */
     double kernel_ms;        /* device time of the step loop (HIP events)          */
-    double gemm_ms;          /* device time of the contraction launches (events)   */
-    int64_t gemm_launches;   /* number of contraction launches                     */
-    double gemm_flops;       /* algorithmic flops of the contractions              */
+    double stage1_ms;        /* timing = 1: summed device time of the predictor    */
+    int64_t stage1_launches; /* contraction launches (HIP events around each) and  */
+    double stage2_ms;        /* of the corrector contraction launches              */
+    int64_t stage2_launches;
+    double gemm_flops;       /* algorithmic flops of all contractions of the run   */
     /* two-time (n_lags > 0): C(l) = Csym(l) + kappa i (chi_xx + chi_yy
        + i chi_yx - i chi_xy) (Eq. (S3) and the Kubo correction after it);
        spectrum S(omega) = 2 Re int_0^inf e^{i omega t} C(t) dt (trapezoid on

@@ -48,8 +48,9 @@ class _Obs(C.Structure):
     _fields_ = ([(n, C.c_double) for n in _OBS_DOUBLES1] +
                 [("n_samples", C.c_int64), ("n_lags", C.c_int64), ("lag_stride", C.c_int64),
                  ("max_norm_dev", C.c_double), ("step_criterion", C.c_double), ("nan_flag", C.c_int32),
-                 ("tile_config", C.c_int32), ("kernel_ms", C.c_double), ("gemm_ms", C.c_double),
-                 ("gemm_launches", C.c_int64), ("gemm_flops", C.c_double), ("linewidth", C.c_double),
+                 ("tile_config", C.c_int32), ("kernel_ms", C.c_double), ("stage1_ms", C.c_double),
+                 ("stage1_launches", C.c_int64), ("stage2_ms", C.c_double), ("stage2_launches", C.c_int64),
+                 ("gemm_flops", C.c_double), ("linewidth", C.c_double),
                  ("linewidth_sym", C.c_double)])
 
 

@@ -79,13 +79,8 @@ __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
     return (uint16_t)(u >> 16);
 }
 
-union Frag16 {
-    uint4 u;
-    double d[2];
-    float f[4];
-    bf16x8 b;
-    f16x8 h;
-};
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 template <int PREC>
 struct Prec;
@@ -101,11 +96,9 @@ struct Prec<TWA_PREC_FP64> {
     __device__ static __forceinline__ int arow(int m) { return 4 * (m & 3) + (m >> 2); }
     __device__ static __forceinline__ G to_g(S v) { return v; }
     __device__ static __forceinline__ void mma(AV& c, const uint4& a, const uint4& b) {
-        Frag16 fa, fb;
-        fa.u = a;
-        fb.u = b;
-        c = __builtin_amdgcn_mfma_f64_16x16x4f64(fa.d[0], fb.d[0], c, 0, 0, 0);
-        c = __builtin_amdgcn_mfma_f64_16x16x4f64(fa.d[1], fb.d[1], c, 0, 0, 0);
+        const f64x2 fa = __builtin_bit_cast(f64x2, a), fb = __builtin_bit_cast(f64x2, b);
+        c = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[0], fb[0], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[1], fb[1], c, 0, 0, 0);
     }
 };
 
@@ -118,11 +111,11 @@ struct Prec<TWA_PREC_FP32> {
     typedef f32x4 AV;
     __device__ static __forceinline__ G to_g(S v) { return v; }
     __device__ static __forceinline__ void mma(AV& c, const uint4& a, const uint4& b) {
-        Frag16 fa, fb;
-        fa.u = a;
-        fb.u = b;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) c = __builtin_amdgcn_mfma_f32_16x16x4f32(fa.f[j], fb.f[j], c, 0, 0, 0);
+        const f32x4 fa = __builtin_bit_cast(f32x4, a), fb = __builtin_bit_cast(f32x4, b);
+        c = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[0], fb[0], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[1], fb[1], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[2], fb[2], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[3], fb[3], c, 0, 0, 0);
     }
 };
 
@@ -135,10 +128,8 @@ struct Prec<TWA_PREC_BF16> {
     typedef f32x4 AV;
     __device__ static __forceinline__ G to_g(S v) { return G{f32_to_bf16_rne(v)}; }
     __device__ static __forceinline__ void mma(AV& c, const uint4& a, const uint4& b) {
-        Frag16 fa, fb;
-        fa.u = a;
-        fb.u = b;
-        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa.b, fb.b, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
+                                                    0, 0, 0);
     }
 };
 
@@ -151,10 +142,8 @@ struct Prec<TWA_PREC_FP16> {
     typedef f32x4 AV;
     __device__ static __forceinline__ G to_g(S v) { return (_Float16)v; }
     __device__ static __forceinline__ void mma(AV& c, const uint4& a, const uint4& b) {
-        Frag16 fa, fb;
-        fa.u = a;
-        fb.u = b;
-        c = __builtin_amdgcn_mfma_f32_16x16x32_f16(fa.h, fb.h, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, a), __builtin_bit_cast(f16x8, b), c, 0,
+                                                   0, 0);
     }
 };
 

@@ -33,7 +33,7 @@ struct Status {
 // K bytes per LDS stage, waves along M, waves along N).
 struct TileCfg {
     int id;
-    int mt, nt, kbytes, waves_m, waves_n;
+    int mt, nt, kbytes, waves_m, waves_n, nstage;
     const char* name;
 };
 int n_tile_cfgs();

@@ -93,7 +93,7 @@ int run_single(const twa_params* p, int64_t n_traj, double dt, int64_t n_steps, 
         }
     }
     int cfg = p->tile_config >= 0 ? p->tile_config : pick_tile_cfg(p->precision, N, B);
-    if (cfg >= n_tile_cfgs()) {
+    if (cfg >= n_tile_cfgs() || (p->precision == TWA_PREC_FP64 && cfg > 3)) {
         set_error("twa_run: unknown tile configuration");
         return TWA_EINVAL;
     }
@@ -259,8 +259,10 @@ int run_single(const twa_params* p, int64_t n_traj, double dt, int64_t n_steps, 
         if (tm) {
             tm->s1.harvest(st);
             tm->s2.harvest(st);
-            out->gemm_ms = tm->s1.total_ms + tm->s2.total_ms;
-            out->gemm_launches = tm->s1.count + tm->s2.count;
+            out->stage1_ms = tm->s1.total_ms;
+            out->stage1_launches = tm->s1.count;
+            out->stage2_ms = tm->s2.total_ms;
+            out->stage2_launches = tm->s2.count;
         }
         // algorithmic contraction flops: stage 1 2*N*(2N)*(2B), stage 2 2*N*N*(2B);
         // response copies: 2 copies x 2*N*N*(2B) per stage

@@ -35,6 +35,7 @@ struct GemmArgs {
     int64_t x_copy;     // element offset between copies
     int64_t K;          // contraction length
     int64_t P, Bp, nmt;
+    int nnt;            // column tiles
     S c1, c2;
     // primal buffers
     const S* s_cur;
@@ -90,7 +91,7 @@ __device__ __forceinline__ void stg4(typename Prec<PREC>::G* p, const typename P
 
 // ---------------------------------------------------------------------------
 // contraction + fused Heun stage
-template <int PREC, int MT, int NT, int KB, int WMW, int WNW, int STAGE, bool TAN>
+template <int PREC, int MT, int NT, int KB, int WMW, int WNW, int NST, int STAGE, bool TAN>
 __global__ __launch_bounds__(64 * WMW * WNW) void heun_stage_kernel(GemmArgs<PREC> a) {
     typedef typename Prec<PREC>::G G;
     typedef typename Prec<PREC>::S S;
@@ -98,23 +99,49 @@ __global__ __launch_bounds__(64 * WMW * WNW) void heun_stage_kernel(GemmArgs<PRE
     constexpr int NTHR = 64 * WMW * WNW;
     constexpr int WM = MT / WMW, WN = NT / WNW;
     constexpr int BI = WM / 16, BJ = WN / 16;
-    constexpr int RS = KB + 16;              // LDS row stride (bytes)
     constexpr int PCS = KB / 16;             // 16-byte pieces per row
     constexpr int PA = MT * PCS, PX = NT * PCS;
-    constexpr int PT = (PA + PX) / NTHR;
     constexpr int KT = KB / (int)sizeof(G);
     constexpr int NTRJ = NT / 2;             // trajectories per tile
-    static_assert((PA + PX) % NTHR == 0, "tile loads must divide evenly");
     static_assert(WM % 16 == 0 && WN % 32 == 0, "wave tile");
     static_assert(KB % 64 == 0, "K stage");
 
-    __shared__ __attribute__((aligned(16))) char lds[2 * (MT + NT) * RS];
+    // NST LDS stages (a ring), each rows [0, MT) of A then [MT, MT + NT) of X,
+    // KB bytes per row; inside every 16-row block the 16-byte piece c of row r
+    // is stored at piece position c ^ swz(r), which makes the 16-lane fragment
+    // reads of one MFMA operand hit distinct LDS banks.  The stages are
+    // distinct LDS objects so that the compiler can tell the loads in flight
+    // into one stage from the reads of another.
+    static_assert(NST >= 2 && NST <= 8, "LDS ring depth");
+    constexpr int SB = (MT + NT) * KB;
+    __shared__ __attribute__((aligned(1024))) char L0[SB];
+    __shared__ __attribute__((aligned(1024))) char L1[SB];
+    __shared__ __attribute__((aligned(1024))) char L2[NST > 2 ? SB : 16];
+    __shared__ __attribute__((aligned(1024))) char L3[NST > 3 ? SB : 16];
+    __shared__ __attribute__((aligned(1024))) char L4[NST > 4 ? SB : 16];
+    __shared__ __attribute__((aligned(1024))) char L5[NST > 5 ? SB : 16];
+    __shared__ __attribute__((aligned(1024))) char L6[NST > 6 ? SB : 16];
+    __shared__ __attribute__((aligned(1024))) char L7[NST > 7 ? SB : 16];
     __shared__ S sS[NTRJ][2];      // primal collective sums of the trajectories of the tile
     __shared__ S sT[NTRJ][2];      // tangent collective sums
     __shared__ S sG[NTRJ][2];      // collective normals
     __shared__ S red[WMW][NTRJ][3];
 
-    const int mt = blockIdx.x, nt = blockIdx.y, cp = blockIdx.z;
+    // XCD-aware tile order: workgroups are dispatched round-robin over the 8
+    // XCDs, so workgroup b runs on XCD b % 8.  Each XCD is given a contiguous
+    // range of tiles ordered M-tile-major, so the workgroups resident on one
+    // XCD share the same rows of A (and walk K together) in that XCD's L2.
+    int mt, nt;
+    {
+        const int nnt = a.nnt;            // column tiles
+        const int T = (int)gridDim.x;     // total tiles = nmt * nnt
+        const int q = T / 8, r = T % 8;
+        const int b = (int)blockIdx.x, x = b % 8, j = b / 8;
+        const int L = x * q + (x < r ? x : r) + j;
+        mt = L / nnt;
+        nt = L % nnt;
+    }
+    const int cp = blockIdx.z;
     const int64_t m0 = (int64_t)mt * MT, n0 = (int64_t)nt * NT;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave % WMW, wn = wave / WMW;
@@ -158,56 +185,84 @@ __global__ __launch_bounds__(64 * WMW * WNW) void heun_stage_kernel(GemmArgs<PRE
     const char* Xg = reinterpret_cast<const char*>(a.X + cp * a.x_copy + n0 * a.ldx);
     const int64_t lda_b = a.lda * (int64_t)sizeof(G), ldx_b = a.ldx * (int64_t)sizeof(G);
     const int nk = (int)(a.K / KT);
-    uint4 pre[PT];
-
-    auto gload = [&](int kt) {
+    // Direct global -> LDS loads (global_load_lds_dwordx4): one wave
+    // instruction moves 64 x 16 bytes into 1 KB of LDS, lane i to offset 16 i,
+    // so each lane fetches the global piece that belongs at its slot.
+    constexpr int RPC = 1024 / KB;                 // rows per 1 KB chunk
+    constexpr int NCH = (MT + NT) / RPC;           // chunks per stage
+    constexpr int NWV = NTHR / 64;
+    constexpr int CPW = NCH / NWV;                 // chunks per wave per stage
+    static_assert(NCH % NWV == 0 && MT % RPC == 0, "chunking");
+    auto swz = [](int r16) { return (r16 / (16 / PCS)) % PCS; };
+    const int wv = __builtin_amdgcn_readfirstlane(wave);
+    const char* src[CPW];
 #pragma unroll
-        for (int p = 0; p < PT; ++p) {
-            const int idx = tid + p * NTHR;
-            if (idx < PA) {
-                const int row = idx / PCS, pc = idx % PCS;
-                pre[p] = *reinterpret_cast<const uint4*>(Ag + row * lda_b + (int64_t)kt * KB + pc * 16);
-            } else {
-                const int j = idx - PA;
-                const int row = j / PCS, pc = j % PCS;
-                pre[p] = *reinterpret_cast<const uint4*>(Xg + row * ldx_b + (int64_t)kt * KB + pc * 16);
+    for (int j = 0; j < CPW; ++j) {
+        const int q = wv + j * NWV;
+        const int row = q * RPC + lane / PCS;
+        const int pc = (lane % PCS) ^ swz(row & 15);
+        src[j] = row < MT ? Ag + row * lda_b + pc * 16 : Xg + (int64_t)(row - MT) * ldx_b + pc * 16;
+    }
+    typedef __attribute__((address_space(3))) char lds_t;
+    typedef const __attribute__((address_space(1))) void gptr_t;
+#define TWA_DMA(KT_, BUF_)                                                                              \
+    do {                                                                                                \
+        const int64_t kofs_ = (int64_t)(KT_) * KB;                                                      \
+        _Pragma("unroll") for (int j = 0; j < CPW; ++j) __builtin_amdgcn_global_load_lds(               \
+            (gptr_t*)(src[j] + kofs_), (lds_t*)((BUF_) + (wv + j * NWV) * 1024), 16, 0, 0);              \
+    } while (0)
+
+    // fragment read offsets of this lane (row within a 16-row block, swizzle)
+    const int ra = Prec<PREC>::arow(lane & 15), rx = lane & 15;
+    const int offA = (wm0 + ra) * KB, offX = (MT + wn0 + rx) * KB;
+    const int swA = swz(ra), swX = swz(rx), grp = lane >> 4;
+#define TWA_COMPUTE(BUF_)                                                                               \
+    do {                                                                                                \
+        _Pragma("unroll") for (int seg = 0; seg < KB / 64; ++seg) {                                     \
+            uint4 af[BI], xf[BJ];                                                                       \
+            const int c_ = seg * 4 + grp;                                                               \
+            _Pragma("unroll") for (int i = 0; i < BI; ++i) af[i] = *reinterpret_cast<const uint4*>(     \
+                (BUF_) + offA + 16 * i * KB + ((c_ ^ swA) << 4));                                       \
+            _Pragma("unroll") for (int j = 0; j < BJ; ++j) xf[j] = *reinterpret_cast<const uint4*>(     \
+                (BUF_) + offX + 16 * j * KB + ((c_ ^ swX) << 4));                                       \
+            _Pragma("unroll") for (int i = 0; i < BI; ++i)                                              \
+                _Pragma("unroll") for (int j = 0; j < BJ; ++j) Prec<PREC>::mma(acc[i][j], af[i], xf[j]); \
+        }                                                                                               \
+    } while (0)
+#define TWA_BUF(I_) ((I_) == 0 ? L0 : (I_) == 1 ? L1 : (I_) == 2 ? L2 : (I_) == 3 ? L3 : \
+                     (I_) == 4 ? L4 : (I_) == 5 ? L5 : (I_) == 6 ? L6 : L7)
+    // vmcnt-only wait (expcnt and lgkmcnt left at their maxima), gfx9 encoding
+#define TWA_WAIT_VM(N_) __builtin_amdgcn_s_waitcnt(((N_) & 15) | (((N_) >> 4) << 14) | (7 << 4) | (15 << 8))
+
+    // prologue: stages 0 .. NST-2 in flight
+#pragma unroll
+    for (int u = 0; u < NST - 1; ++u)
+        if (u < nk) TWA_DMA(u, TWA_BUF(u));
+    for (int kt0 = 0; kt0 < nk; kt0 += NST) {
+#pragma unroll
+        for (int u = 0; u < NST; ++u) {
+            const int kt = kt0 + u;
+            if (kt < nk) {
+                // stage kt has landed once at most the later stages are pending
+                if (nk - 1 - kt >= NST - 2) TWA_WAIT_VM((NST - 2) * CPW);
+                else TWA_WAIT_VM(0);
+                // Barrier without a memory fence: a fence would wait for every
+                // load still in flight into the later stages.  What it has to
+                // order is covered explicitly: this wave's loads into stage kt
+                // completed (vmcnt above), and its reads of the stage the next
+                // load overwrites were consumed by MFMAs before this point.
+                __builtin_amdgcn_s_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+                if (kt + NST - 1 < nk) TWA_DMA(kt + NST - 1, TWA_BUF((u + NST - 1) % NST));
+                __builtin_amdgcn_sched_barrier(0);
+                TWA_COMPUTE(TWA_BUF(u));
             }
         }
-    };
-    auto sstore = [&](int buf) {
-        char* base = lds + buf * (MT + NT) * RS;
-#pragma unroll
-        for (int p = 0; p < PT; ++p) {
-            const int idx = tid + p * NTHR;
-            const int row = idx / PCS, pc = idx % PCS;   // rows MT.. are the X tile
-            *reinterpret_cast<uint4*>(base + row * RS + pc * 16) = pre[p];
-        }
-    };
-
-    gload(0);
-    sstore(0);
-    __syncthreads();
-    for (int kt = 0; kt < nk; ++kt) {
-        if (kt + 1 < nk) gload(kt + 1);
-        const char* base = lds + (kt & 1) * (MT + NT) * RS;
-#pragma unroll
-        for (int seg = 0; seg < KB / 64; ++seg) {
-            uint4 af[BI], xf[BJ];
-            const int off = seg * 64 + (lane >> 4) * 16;
-#pragma unroll
-            for (int i = 0; i < BI; ++i)
-                af[i] = *reinterpret_cast<const uint4*>(base + (wm0 + 16 * i + Prec<PREC>::arow(lane & 15)) * RS + off);
-#pragma unroll
-            for (int j = 0; j < BJ; ++j)
-                xf[j] = *reinterpret_cast<const uint4*>(base + (MT + wn0 + 16 * j + (lane & 15)) * RS + off);
-#pragma unroll
-            for (int i = 0; i < BI; ++i)
-#pragma unroll
-                for (int j = 0; j < BJ; ++j) Prec<PREC>::mma(acc[i][j], af[i], xf[j]);
-        }
-        if (kt + 1 < nk) sstore((kt + 1) & 1);
-        __syncthreads();
     }
+#undef TWA_DMA
+#undef TWA_COMPUTE
+#undef TWA_BUF
+#undef TWA_WAIT_VM
 
     // ---- epilogue: fused Heun stage on (spin i, trajectory k)
     const S c1 = a.c1, c2 = a.c2;
@@ -391,25 +446,31 @@ __global__ __launch_bounds__(64 * WMW * WNW) void heun_stage_kernel(GemmArgs<PRE
 // ---------------------------------------------------------------------------
 // tile configurations
 static const TileCfg kCfgs[] = {
-    {0, 16, 32, 64, 1, 1, "16x32x64B-1w"},
-    {1, 64, 64, 64, 2, 2, "64x64x64B-4w"},
-    {2, 128, 128, 128, 2, 2, "128x128x128B-4w"},
-    {3, 128, 128, 64, 2, 2, "128x128x64B-4w"},
+    {0, 16, 32, 64, 1, 1, 2, "16x32 K64B 1w 2st"},
+    {1, 64, 64, 64, 2, 2, 4, "64x64 K64B 4w 4st"},
+    {2, 128, 128, 128, 2, 2, 4, "128x128 K128B 4w 4st"},
+    {3, 128, 128, 64, 2, 2, 8, "128x128 K64B 4w 8st"},
+    {4, 256, 128, 64, 4, 1, 6, "256x128 K64B 4w 6st"},
+    {5, 128, 256, 64, 2, 2, 6, "128x256 K64B 4w 6st"},
+    {6, 256, 256, 64, 4, 2, 4, "256x256 K64B 8w 4st"},
 };
 int n_tile_cfgs() { return (int)(sizeof(kCfgs) / sizeof(kCfgs[0])); }
 const TileCfg& tile_cfg(int id) { return kCfgs[id]; }
 
 template <int PREC, int CFG>
 struct CfgT;
-#define TWA_CFG(ID, MT_, NT_, KB_, WM_, WN_)      \
-    template <int PREC>                           \
-    struct CfgT<PREC, ID> {                       \
-        static constexpr int MT = MT_, NT = NT_, KB = KB_, WMW = WM_, WNW = WN_; \
+#define TWA_CFG(ID, MT_, NT_, KB_, WM_, WN_, NST_)  \
+    template <int PREC>                             \
+    struct CfgT<PREC, ID> {                         \
+        static constexpr int MT = MT_, NT = NT_, KB = KB_, WMW = WM_, WNW = WN_, NST = NST_; \
     };
-TWA_CFG(0, 16, 32, 64, 1, 1)
-TWA_CFG(1, 64, 64, 64, 2, 2)
-TWA_CFG(2, 128, 128, 128, 2, 2)
-TWA_CFG(3, 128, 128, 64, 2, 2)
+TWA_CFG(0, 16, 32, 64, 1, 1, 2)
+TWA_CFG(1, 64, 64, 64, 2, 2, 4)
+TWA_CFG(2, 128, 128, 128, 2, 2, 4)
+TWA_CFG(3, 128, 128, 64, 2, 2, 8)
+TWA_CFG(4, 256, 128, 64, 4, 1, 6)
+TWA_CFG(5, 128, 256, 64, 2, 2, 6)
+TWA_CFG(6, 256, 256, 64, 4, 2, 4)
 
 template <int PREC, int CFG>
 static int launch_gemm_t(const Geometry& g, const EnsembleBuffers& b, const StepConsts& c, int stage,
@@ -480,18 +541,20 @@ static int launch_gemm_t(const Geometry& g, const EnsembleBuffers& b, const Step
             a.ldxn = P;
         }
     }
-    dim3 grid((unsigned)(P / C::MT), (unsigned)(g.C2 / C::NT), (unsigned)ncopy);
+    // grid.x enumerates all (M tile, column tile) pairs; each block derives its tile
+    a.nnt = (int)(g.C2 / C::NT);
+    dim3 grid((unsigned)((P / C::MT) * (g.C2 / C::NT)), 1u, (unsigned)ncopy);
     dim3 block(64 * C::WMW * C::WNW);
     if (stage == 1) {
         if (tangent)
-            hipLaunchKernelGGL((heun_stage_kernel<PREC, C::MT, C::NT, C::KB, C::WMW, C::WNW, 1, true>), grid, block, 0, st, a);
+            hipLaunchKernelGGL((heun_stage_kernel<PREC, C::MT, C::NT, C::KB, C::WMW, C::WNW, C::NST, 1, true>), grid, block, 0, st, a);
         else
-            hipLaunchKernelGGL((heun_stage_kernel<PREC, C::MT, C::NT, C::KB, C::WMW, C::WNW, 1, false>), grid, block, 0, st, a);
+            hipLaunchKernelGGL((heun_stage_kernel<PREC, C::MT, C::NT, C::KB, C::WMW, C::WNW, C::NST, 1, false>), grid, block, 0, st, a);
     } else {
         if (tangent)
-            hipLaunchKernelGGL((heun_stage_kernel<PREC, C::MT, C::NT, C::KB, C::WMW, C::WNW, 2, true>), grid, block, 0, st, a);
+            hipLaunchKernelGGL((heun_stage_kernel<PREC, C::MT, C::NT, C::KB, C::WMW, C::WNW, C::NST, 2, true>), grid, block, 0, st, a);
         else
-            hipLaunchKernelGGL((heun_stage_kernel<PREC, C::MT, C::NT, C::KB, C::WMW, C::WNW, 2, false>), grid, block, 0, st, a);
+            hipLaunchKernelGGL((heun_stage_kernel<PREC, C::MT, C::NT, C::KB, C::WMW, C::WNW, C::NST, 2, false>), grid, block, 0, st, a);
     }
     TWA_HIP_CHECK(hipGetLastError());
     return TWA_OK;
@@ -505,6 +568,13 @@ static int launch_gemm_p(const Geometry& g, const EnsembleBuffers& b, const Step
         case 1: return launch_gemm_t<PREC, 1>(g, b, c, stage, tangent, cur, store_y2, st);
         case 2: return launch_gemm_t<PREC, 2>(g, b, c, stage, tangent, cur, store_y2, st);
         case 3: return launch_gemm_t<PREC, 3>(g, b, c, stage, tangent, cur, store_y2, st);
+    }
+    if constexpr (PREC != TWA_PREC_FP64) {
+        switch (g.cfg) {
+            case 4: return launch_gemm_t<PREC, 4>(g, b, c, stage, tangent, cur, store_y2, st);
+            case 5: return launch_gemm_t<PREC, 5>(g, b, c, stage, tangent, cur, store_y2, st);
+            case 6: return launch_gemm_t<PREC, 6>(g, b, c, stage, tangent, cur, store_y2, st);
+        }
     }
     set_error("unknown tile configuration");
     return TWA_EINVAL;
