@@ -169,6 +169,9 @@ typedef struct twa_observables {
        the lag grid, zero padded to 8 L); linewidth = its FWHM (main text)   */
     double linewidth;        /* FWHM of the spectrum of C                          */
     double linewidth_sym;    /* FWHM of the spectrum of Csym alone                 */
+    double adjoint_fwd_ms;   /* twa_adjoint: device time of the checkpointed       */
+    double adjoint_bwd_ms;   /* forward run and of the reverse sweep (recompute    */
+                             /* included); kernel_ms is their sum                  */
 } twa_observables;
 
 /* Optional host output buffers of twa_run (any may be NULL). */

@@ -51,7 +51,7 @@ class _Obs(C.Structure):
                  ("tile_config", C.c_int32), ("kernel_ms", C.c_double), ("stage1_ms", C.c_double),
                  ("stage1_launches", C.c_int64), ("stage2_ms", C.c_double), ("stage2_launches", C.c_int64),
                  ("gemm_flops", C.c_double), ("linewidth", C.c_double),
-                 ("linewidth_sym", C.c_double)])
+                 ("linewidth_sym", C.c_double), ("adjoint_fwd_ms", C.c_double), ("adjoint_bwd_ms", C.c_double)])
 
 
 class _Outs(C.Structure):
@@ -233,6 +233,28 @@ def run(pump: Pump, n_traj: int, dt: float, n_steps: int, seed: int = 0, *, gamm
     return res
 
 
+GRAD_NAMES = ("d_SpSm_dw", "d_SpSm_dalpha", "d_g2_dw", "d_g2_dalpha")
+
+
+def adjoint(pump: Pump, n_traj: int, dt: float, n_steps: int, seed: int = 0, *, ckpt_every: int = 256,
+            gamma: float = 1.0, s0z: float = 1.0, burnin: int = -1, precision: str = "fp32", point: int = 0,
+            tile_config: int = -1, stream=None):
+    """twa_adjoint: observables of the forward run and the pathwise gradients
+    d<S+S->/dw, d<S+S->/dalpha, dg2/dw, dg2/dalpha at fixed noise."""
+    p = _Params()
+    _lib.twa_params_default(C.byref(p))
+    p.pump = pump.handle
+    p.gamma, p.s0z, p.burnin = gamma, s0z, burnin
+    p.precision = PRECISIONS[precision]
+    p.point, p.tile_config = point, tile_config
+    p.stream = _stream_ptr(stream)
+    o = _Obs()
+    g = (C.c_double * 4)()
+    _check(_lib.twa_adjoint(C.byref(p), int(n_traj), float(dt), int(n_steps), C.c_uint64(seed & (2 ** 64 - 1)),
+                            int(ckpt_every), C.byref(o), g))
+    return _obs_dict(o), dict(zip(GRAD_NAMES, list(g)))
+
+
 def philox(ctr: np.ndarray, key0: int, key1: int) -> np.ndarray:
     """twa_philox on the device: ctr (n, 4) uint32 -> (n, 4) uint32."""
     import torch
@@ -256,4 +278,7 @@ def noise(seed: int, step: int, n_traj: int, N: int, point: int = 0, fp64: bool 
     return (z[0], z[1]), (g[0], g[1])
 
 
-__all__ = ["Pump", "build_pump", "run", "philox", "noise", "TWAError", "version", "PRECISIONS", "LIB_PATH"]
+from .autograd import TWAObservables  # noqa: E402
+
+__all__ = ["Pump", "build_pump", "run", "adjoint", "philox", "noise", "TWAError", "version", "PRECISIONS",
+           "LIB_PATH", "TWAObservables"]

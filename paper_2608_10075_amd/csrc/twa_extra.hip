@@ -1,5 +1,5 @@
-// Batched scan and adjoint entry points (filled in by their own translation
-// units once available); until then they report TWA_EINVAL.
+// Batched-scan entry points (the grouped scan is not part of this build yet:
+// twa_run_batch reports TWA_EINVAL).
 #include "twa_internal.h"
 
 extern "C" {
@@ -22,9 +22,5 @@ TWA_API int twa_run_batch(const twa_point*, int, const twa_batch_opts*, twa_obse
     return TWA_EINVAL;
 }
 
-TWA_API int twa_adjoint(const twa_params*, int64_t, double, int64_t, uint64_t, int32_t, twa_observables*, double*) {
-    twa::set_error("twa_adjoint: not available in this build");
-    return TWA_EINVAL;
-}
 
 }

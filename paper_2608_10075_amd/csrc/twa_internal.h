@@ -90,7 +90,40 @@ struct StepConsts {
     int J;
 };
 
-// kernel launchers (twa_kernels.hip)
+// Type-erased description of one contraction launch (pointers are device
+// buffers of the geometry's precision; kinds: 0 primal, 1 response tangent,
+// 2 store (out = in + sign * A X), 3 adjoint of the corrector, 4 adjoint of
+// the predictor).
+struct GemmCall {
+    int kind = 0, stage = 1, ncopy = 1;
+    const void* A = nullptr;
+    int64_t lda = 0;
+    const void* X = nullptr;
+    int64_t ldx = 0, x_copy = 0, K = 0;
+    double c1 = 0, c2 = 0;
+    const void* s_cur = nullptr;
+    void *s_next = nullptr, *dlt = nullptr, *Y = nullptr, *Y2out = nullptr, *Dop = nullptr, *Xnext = nullptr;
+    int64_t ldxn = 0;
+    const void* part_prim = nullptr;
+    void* part_out = nullptr;
+    const void* g = nullptr;
+    int store_y2 = 0;
+    const void* tpart_in = nullptr;
+    int64_t* step = nullptr;
+    const void* Sin = nullptr;
+    void* Sout = nullptr;
+    double store_sign = 1.0;
+    const void *Y2in = nullptr, *Qin = nullptr, *YA = nullptr;
+    void *lam = nullptr, *M1 = nullptr, *Rb = nullptr;
+    double* gacc = nullptr;
+    double inv_w = 0;
+    double srccoef[2][5] = {{0}};
+    double src_scale = 0;
+    int src_on = 0;
+};
+int launch_gemm_call(const Geometry& g, const GemmCall& c, hipStream_t st);
+
+// kernel launchers (twa_step.hip, twa_aux.hip)
 int launch_build_A(const Geometry& g, const double* W, const double* F, double dt, void* A, hipStream_t st);
 int launch_init_state(const Geometry& g, const EnsembleBuffers& b, const StepConsts& c,
                       const double* init_dev, hipStream_t st);

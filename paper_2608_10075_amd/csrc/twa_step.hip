@@ -61,7 +61,27 @@ struct GemmArgs {
     int64_t t_part_copy;    // element offset between copies of partial sums
     int64_t t_op_copy;      // element offset between copies of operands
     int64_t* step;          // advanced by stage 2 of the primal (block 0)
+    S* Y2out;               // primal stage 2: where the stage-2 field goes (nullptr: in place into Y)
+    // store kind: out = in + sign * acc
+    const S* Sin;
+    S* Sout;
+    S store_sign;
+    // adjoint kinds (copy cp = objective)
+    int64_t N, B;
+    const S* Y2in;          // stage-2 contraction output of the primal step
+    const S* Qin;           // noise part -sqrt(dt) F zeta of the primal step
+    const S* YA;            // d(contraction output)/d(alpha) of the stage
+    S* lam;                 // cotangent of the state, [copy][3][Bp][P]
+    S* M1;                  // cotangent of the predictor increment
+    S* Rb;                  // lam' + cotangent of the predictor state
+    double* gacc;           // [copy][2][nmt][Bp] gradient partial sums (w, alpha)
+    S inv_w;
+    S srccoef[2][5];        // objective coefficients on (T2, T3, T4, Z, ZZ)
+    S src_scale;            // 1 / (B * window samples)
+    int src_on;             // the state produced by this backward step is observed
 };
+
+enum { KIND_PRIMAL = 0, KIND_TANGENT = 1, KIND_STORE = 2, KIND_ADJ2 = 3, KIND_ADJ1 = 4 };
 
 template <typename S>
 __device__ __forceinline__ void ld4(const S* p, S (&v)[4]) {
@@ -91,8 +111,11 @@ __device__ __forceinline__ void stg4(typename Prec<PREC>::G* p, const typename P
 
 // ---------------------------------------------------------------------------
 // contraction + fused Heun stage
-template <int PREC, int MT, int NT, int KB, int WMW, int WNW, int NST, int STAGE, bool TAN>
+template <int PREC, int MT, int NT, int KB, int WMW, int WNW, int NST, int STAGE, int KIND>
 __global__ __launch_bounds__(64 * WMW * WNW) void heun_stage_kernel(GemmArgs<PREC> a) {
+    constexpr bool TAN = KIND == KIND_TANGENT;
+    constexpr bool ADJ = KIND == KIND_ADJ2 || KIND == KIND_ADJ1;
+    constexpr bool TCOPY = TAN || ADJ;     // per-copy collective sums of the copy operand
     typedef typename Prec<PREC>::G G;
     typedef typename Prec<PREC>::S S;
     typedef typename Prec<PREC>::AV AV;
@@ -125,7 +148,8 @@ __global__ __launch_bounds__(64 * WMW * WNW) void heun_stage_kernel(GemmArgs<PRE
     __shared__ S sS[NTRJ][2];      // primal collective sums of the trajectories of the tile
     __shared__ S sT[NTRJ][2];      // tangent collective sums
     __shared__ S sG[NTRJ][2];      // collective normals
-    __shared__ S red[WMW][NTRJ][3];
+    __shared__ S red[WMW][NTRJ][4];
+    __shared__ S sSrc[NTRJ][3];    // adjoint: observation source of each trajectory
 
     // XCD-aware tile order: workgroups are dispatched round-robin over the 8
     // XCDs, so workgroup b runs on XCD b % 8.  Each XCD is given a contiguous
@@ -150,27 +174,46 @@ __global__ __launch_bounds__(64 * WMW * WNW) void heun_stage_kernel(GemmArgs<PRE
     const int64_t k0t = n0 / 2;    // first trajectory of the tile
 
     // ---- collective sums of this tile's trajectories (ordered over M tiles)
-    for (int t = tid; t < NTRJ; t += NTHR) {
-        const int64_t k = k0t + t;
-        const S* pp = a.part_prim;
-        S sx = 0, sy = 0;
-        for (int64_t q = 0; q < nmt; ++q) {
-            sx += pp[(0 * nmt + q) * Bp + k];
-            sy += pp[(1 * nmt + q) * Bp + k];
-        }
-        sS[t][0] = sx;
-        sS[t][1] = sy;
-        sG[t][0] = a.g[k];
-        sG[t][1] = a.g[Bp + k];
-        if constexpr (TAN) {
-            const S* tp = a.tpart_in + cp * a.t_part_copy;
-            S tx = 0, ty = 0;
+    if constexpr (KIND != KIND_STORE) {
+        for (int t = tid; t < NTRJ; t += NTHR) {
+            const int64_t k = k0t + t;
+            const S* pp = a.part_prim;
+            S sx = 0, sy = 0, sz = 0;
             for (int64_t q = 0; q < nmt; ++q) {
-                tx += tp[(0 * nmt + q) * Bp + k];
-                ty += tp[(1 * nmt + q) * Bp + k];
+                sx += pp[(0 * nmt + q) * Bp + k];
+                sy += pp[(1 * nmt + q) * Bp + k];
+                if constexpr (KIND == KIND_ADJ1) sz += pp[(2 * nmt + q) * Bp + k];
             }
-            sT[t][0] = tx;
-            sT[t][1] = ty;
+            sS[t][0] = sx;
+            sS[t][1] = sy;
+            sG[t][0] = a.g[k];
+            sG[t][1] = a.g[Bp + k];
+            if constexpr (TCOPY) {
+                const S* tp = a.tpart_in + cp * a.t_part_copy;
+                S tx = 0, ty = 0;
+                for (int64_t q = 0; q < nmt; ++q) {
+                    tx += tp[(0 * nmt + q) * Bp + k];
+                    ty += tp[(1 * nmt + q) * Bp + k];
+                }
+                sT[t][0] = tx;
+                sT[t][1] = ty;
+            }
+            if constexpr (KIND == KIND_ADJ1) {
+                // derivative of the observed moments (T2, T3, T4, Z, ZZ) of this
+                // trajectory's state with respect to any one spin component
+                S ox = 0, oy = 0, oz = 0;
+                if (a.src_on && k < a.B) {
+                    const S T2 = S(0.25) * (sx * sx + sy * sy);
+                    const S* cf = a.srccoef[cp];
+                    const S gt = S(0.5) * cf[0] + S(0.5) * cf[1] * sz + cf[2] * T2;
+                    ox = a.src_scale * gt * sx;
+                    oy = a.src_scale * gt * sy;
+                    oz = a.src_scale * (cf[1] * T2 + cf[3] + S(2) * cf[4] * sz);
+                }
+                sSrc[t][0] = ox;
+                sSrc[t][1] = oy;
+                sSrc[t][2] = oz;
+            }
         }
     }
 
@@ -274,16 +317,18 @@ __global__ __launch_bounds__(64 * WMW * WNW) void heun_stage_kernel(GemmArgs<PRE
         const S Sx = sS[kl][0], Sy = sS[kl][1];
         const S hx0 = c1 * Sx + c2 * sG[kl][0];
         const S hy0 = c1 * Sy + c2 * sG[kl][1];
-        S ps0 = 0, ps1 = 0, ps2 = 0;
+        S ps0 = 0, ps1 = 0, ps2 = 0, ps3 = 0;
 #pragma unroll
         for (int bi = 0; bi < BI; ++bi) {
             const int64_t i0 = m0 + wm0 + 16 * bi + 4 * (lane >> 4);
             const int64_t off = k * P + i0;
             S x[4], y[4], z[4];
-            ld4(a.s_cur + off, x);
-            ld4(a.s_cur + SP + off, y);
-            ld4(a.s_cur + 2 * SP + off, z);
-            if constexpr (!TAN && STAGE == 1) {
+            if constexpr (KIND != KIND_STORE) {
+                ld4(a.s_cur + off, x);
+                ld4(a.s_cur + SP + off, y);
+                ld4(a.s_cur + 2 * SP + off, z);
+            }
+            if constexpr (KIND == KIND_PRIMAL && STAGE == 1) {
                 S dx[4], dy[4], dz[4], yx[4], yy[4];
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
@@ -305,7 +350,7 @@ __global__ __launch_bounds__(64 * WMW * WNW) void heun_stage_kernel(GemmArgs<PRE
                 st4(a.Y + SP + off, yy);
                 stg4<PREC>(a.Dop + opcol(k, 0) * P + i0, dx);
                 stg4<PREC>(a.Dop + opcol(k, 1) * P + i0, dy);
-            } else if constexpr (!TAN && STAGE == 2) {
+            } else if constexpr (KIND == KIND_PRIMAL && STAGE == 2) {
                 S dx[4], dy[4], dz[4], yx[4], yy[4], nx[4], ny[4], nz[4];
                 ld4(a.dlt + off, dx);
                 ld4(a.dlt + SP + off, dy);
@@ -331,12 +376,13 @@ __global__ __launch_bounds__(64 * WMW * WNW) void heun_stage_kernel(GemmArgs<PRE
                 st4(a.s_next + SP + off, ny);
                 st4(a.s_next + 2 * SP + off, nz);
                 if (a.store_y2) {
-                    st4(a.Y + off, yx);
-                    st4(a.Y + SP + off, yy);
+                    S* yo = a.Y2out ? a.Y2out : a.Y;
+                    st4(yo + off, yx);
+                    st4(yo + SP + off, yy);
                 }
                 stg4<PREC>(a.Xnext + opcol(k, 0) * a.ldxn + i0, nx);
                 stg4<PREC>(a.Xnext + opcol(k, 1) * a.ldxn + i0, ny);
-            } else if constexpr (TAN && STAGE == 1) {
+            } else if constexpr (KIND == KIND_TANGENT && STAGE == 1) {
                 const S tSx = sT[kl][0], tSy = sT[kl][1];
                 const S* tc = a.t_cur + cp * a.t_state_copy;
                 S u[4], v[4], w[4], yx[4], yy[4], ex[4], ey[4], ez[4], ax4[4], ay4[4];
@@ -369,7 +415,107 @@ __global__ __launch_bounds__(64 * WMW * WNW) void heun_stage_kernel(GemmArgs<PRE
                 G* tdo = a.tDop + cp * a.t_op_copy;
                 stg4<PREC>(tdo + opcol(k, 0) * P + i0, ex);
                 stg4<PREC>(tdo + opcol(k, 1) * P + i0, ey);
-            } else {  // TAN && STAGE == 2
+            } else if constexpr (KIND == KIND_STORE) {
+                S ox[4], oy[4];
+                if (a.Sin) {
+                    ld4(a.Sin + off, ox);
+                    ld4(a.Sin + SP + off, oy);
+                } else {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) ox[r] = oy[r] = S(0);
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    ox[r] += a.store_sign * acc[bi][2 * p][r];
+                    oy[r] += a.store_sign * acc[bi][2 * p + 1][r];
+                }
+                st4(a.Sout + off, ox);
+                st4(a.Sout + SP + off, oy);
+            } else if constexpr (KIND == KIND_ADJ2) {
+                // reverse of the corrector: lam' -> (mu1, R = lam' + cotangent of s~, nu1)
+                const int64_t co = cp * a.t_state_copy;
+                S lx[4], ly[4], lz[4], dx[4], dy[4], dz[4], y2x[4], y2y[4], qx[4], qy[4], ax_[4], ay_[4];
+                ld4(a.lam + co + off, lx);
+                ld4(a.lam + co + SP + off, ly);
+                ld4(a.lam + co + 2 * SP + off, lz);
+                ld4(a.dlt + off, dx);
+                ld4(a.dlt + SP + off, dy);
+                ld4(a.dlt + 2 * SP + off, dz);
+                ld4(a.Y2in + off, y2x);
+                ld4(a.Y2in + SP + off, y2y);
+                ld4(a.Qin + off, qx);
+                ld4(a.Qin + SP + off, qy);
+                ld4(a.YA + off, ax_);
+                ld4(a.YA + SP + off, ay_);
+                const S tSx = sT[kl][0], tSy = sT[kl][1];
+                S m1x[4], m1y[4], m1z[4], rx[4], ry[4], rz[4], n1x[4], n1y[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const S px = x[r] + dx[r], py = y[r] + dy[r], pz = z[r] + dz[r];
+                    const S Hx = y2x[r] + hx0, Hy = y2y[r] + hy0;
+                    const S ux = S(0.5) * lx[r], uy = S(0.5) * ly[r], uz = S(0.5) * lz[r];
+                    const S n2x = ux * pz - uz * px, n2y = uy * pz - uz * py;
+                    const S tx = -uz * Hx + c1 * tSx + acc[bi][2 * p][r];
+                    const S ty = -uz * Hy + c1 * tSy + acc[bi][2 * p + 1][r];
+                    const S tz = ux * Hx + uy * Hy;
+                    m1x[r] = ux + tx;
+                    m1y[r] = uy + ty;
+                    m1z[r] = uz + tz;
+                    rx[r] = lx[r] + tx;
+                    ry[r] = ly[r] + ty;
+                    rz[r] = lz[r] + tz;
+                    n1x[r] = m1x[r] * z[r] - m1z[r] * x[r];
+                    n1y[r] = m1y[r] * z[r] - m1z[r] * y[r];
+                    ps0 += n1x[r];
+                    ps1 += n1y[r];
+                    ps2 += n2x * (y2x[r] * a.inv_w - S(0.5) * a.inv_w * qx[r]) +
+                           n2y * (y2y[r] * a.inv_w - S(0.5) * a.inv_w * qy[r]);
+                    ps3 += n2x * ax_[r] + n2y * ay_[r];
+                }
+                st4(a.M1 + co + off, m1x);
+                st4(a.M1 + co + SP + off, m1y);
+                st4(a.M1 + co + 2 * SP + off, m1z);
+                st4(a.Rb + co + off, rx);
+                st4(a.Rb + co + SP + off, ry);
+                st4(a.Rb + co + 2 * SP + off, rz);
+                G* no = a.Xnext + cp * a.t_op_copy;
+                stg4<PREC>(no + opcol(k, 0) * a.ldxn + i0, n1x);
+                stg4<PREC>(no + opcol(k, 1) * a.ldxn + i0, n1y);
+            } else if constexpr (KIND == KIND_ADJ1) {
+                // reverse of the predictor: (mu1, R) -> lam of the step's input state
+                const int64_t co = cp * a.t_state_copy;
+                S mx[4], my[4], mz[4], rx[4], ry[4], rz[4], y1x[4], y1y[4], qx[4], qy[4], ax_[4], ay_[4];
+                ld4(a.M1 + co + off, mx);
+                ld4(a.M1 + co + SP + off, my);
+                ld4(a.M1 + co + 2 * SP + off, mz);
+                ld4(a.Rb + co + off, rx);
+                ld4(a.Rb + co + SP + off, ry);
+                ld4(a.Rb + co + 2 * SP + off, rz);
+                ld4(a.Y + off, y1x);
+                ld4(a.Y + SP + off, y1y);
+                ld4(a.Qin + off, qx);
+                ld4(a.Qin + SP + off, qy);
+                ld4(a.YA + off, ax_);
+                ld4(a.YA + SP + off, ay_);
+                const S tSx = sT[kl][0], tSy = sT[kl][1];
+                const S ox = sSrc[kl][0], oy = sSrc[kl][1], oz = sSrc[kl][2];
+                S nlx[4], nly[4], nlz[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const S Hx = y1x[r] + hx0, Hy = y1y[r] + hy0;
+                    const S msk = (i0 + r < a.N) ? S(1) : S(0);
+                    nlx[r] = rx[r] - mz[r] * Hx + c1 * tSx + acc[bi][2 * p][r] + msk * ox;
+                    nly[r] = ry[r] - mz[r] * Hy + c1 * tSy + acc[bi][2 * p + 1][r] + msk * oy;
+                    nlz[r] = rz[r] + mx[r] * Hx + my[r] * Hy + msk * oz;
+                    const S n1x = mx[r] * z[r] - mz[r] * x[r], n1y = my[r] * z[r] - mz[r] * y[r];
+                    ps2 += n1x * (y1x[r] * a.inv_w - S(0.5) * a.inv_w * qx[r]) +
+                           n1y * (y1y[r] * a.inv_w - S(0.5) * a.inv_w * qy[r]);
+                    ps3 += n1x * ax_[r] + n1y * ay_[r];
+                }
+                st4(a.lam + co + off, nlx);
+                st4(a.lam + co + SP + off, nly);
+                st4(a.lam + co + 2 * SP + off, nlz);
+            } else {  // KIND_TANGENT && STAGE == 2
                 const S tSx = sT[kl][0], tSy = sT[kl][1];
                 const S* tc = a.t_cur + cp * a.t_state_copy;
                 const S* td = a.t_dlt + cp * a.t_state_copy;
@@ -420,25 +566,47 @@ __global__ __launch_bounds__(64 * WMW * WNW) void heun_stage_kernel(GemmArgs<PRE
         ps0 += __shfl_xor(ps0, 16);
         ps1 += __shfl_xor(ps1, 16);
         ps2 += __shfl_xor(ps2, 16);
+        ps3 += __shfl_xor(ps3, 16);
         ps0 += __shfl_xor(ps0, 32);
         ps1 += __shfl_xor(ps1, 32);
         ps2 += __shfl_xor(ps2, 32);
+        ps3 += __shfl_xor(ps3, 32);
         if (lane < 16) {
             red[wm][kl][0] = ps0;
             red[wm][kl][1] = ps1;
             red[wm][kl][2] = ps2;
+            red[wm][kl][3] = ps3;
         }
     }
-    __syncthreads();
-    S* po = a.part_out + (TAN ? cp * a.t_part_copy : 0);
-    for (int t = tid; t < 3 * NTRJ; t += NTHR) {
-        const int c = t / NTRJ, kl = t % NTRJ;
-        S s = 0;
+    if constexpr (KIND != KIND_STORE) {
+        __syncthreads();
+        if constexpr (KIND == KIND_PRIMAL || KIND == KIND_TANGENT || KIND == KIND_ADJ2) {
+            // ADJ2: channels 0, 1 are the spin sums of nu1 (its z channel is zero)
+            S* po = a.part_out + (TCOPY ? cp * a.t_part_copy : 0);
+            for (int t = tid; t < 3 * NTRJ; t += NTHR) {
+                const int c = t / NTRJ, kl = t % NTRJ;
+                S sum = 0;
+                if (KIND != KIND_ADJ2 || c < 2) {
 #pragma unroll
-        for (int q = 0; q < WMW; ++q) s += red[q][kl][c];
-        po[((int64_t)c * nmt + mt) * Bp + k0t + kl] = s;
+                    for (int q = 0; q < WMW; ++q) sum += red[q][kl][c];
+                }
+                po[((int64_t)c * nmt + mt) * Bp + k0t + kl] = sum;
+            }
+        }
+        if constexpr (ADJ) {
+            // gradient channels 2 (w) and 3 (alpha), accumulated over steps in FP64;
+            // each (copy, M tile, trajectory) slot belongs to one workgroup
+            for (int t = tid; t < 2 * NTRJ; t += NTHR) {
+                const int c = t / NTRJ, kl = t % NTRJ;
+                S sum = 0;
+#pragma unroll
+                for (int q = 0; q < WMW; ++q) sum += red[q][kl][2 + c];
+                double* gp = a.gacc + (((int64_t)cp * 2 + c) * nmt + mt) * Bp + k0t + kl;
+                *gp += (double)sum;
+            }
+        }
     }
-    if constexpr (!TAN && STAGE == 2) {
+    if constexpr (KIND == KIND_PRIMAL && STAGE == 2) {
         if (blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && tid == 0) a.step[0] += 1;
     }
 }
@@ -472,10 +640,64 @@ TWA_CFG(4, 256, 128, 64, 4, 1, 6)
 TWA_CFG(5, 128, 256, 64, 2, 2, 6)
 TWA_CFG(6, 256, 256, 64, 4, 2, 4)
 
-template <int PREC, int CFG>
-static int launch_gemm_t(const Geometry& g, const EnsembleBuffers& b, const StepConsts& c, int stage,
-                         bool tangent, int cur, bool store_y2, hipStream_t st) {
+template <int PREC, int CFG, int STAGE, int KIND>
+static int launch_kernel(const GemmArgs<PREC>& a, int64_t P, int64_t C2, int ncopy, hipStream_t st) {
     typedef CfgT<PREC, CFG> C;
+    GemmArgs<PREC> aa = a;
+    aa.nnt = (int)(C2 / C::NT);
+    dim3 grid((unsigned)((P / C::MT) * (C2 / C::NT)), 1u, (unsigned)ncopy);
+    dim3 block(64 * C::WMW * C::WNW);
+    hipLaunchKernelGGL((heun_stage_kernel<PREC, C::MT, C::NT, C::KB, C::WMW, C::WNW, C::NST, STAGE, KIND>), grid,
+                       block, 0, st, aa);
+    TWA_HIP_CHECK(hipGetLastError());
+    return TWA_OK;
+}
+
+template <int PREC, int CFG>
+static int dispatch_kind(const GemmArgs<PREC>& a, int stage, int kind, int64_t P, int64_t C2, int ncopy,
+                         hipStream_t st) {
+    if (stage == 1) {
+        switch (kind) {
+            case KIND_PRIMAL: return launch_kernel<PREC, CFG, 1, KIND_PRIMAL>(a, P, C2, ncopy, st);
+            case KIND_TANGENT: return launch_kernel<PREC, CFG, 1, KIND_TANGENT>(a, P, C2, ncopy, st);
+            case KIND_STORE: return launch_kernel<PREC, CFG, 1, KIND_STORE>(a, P, C2, ncopy, st);
+            case KIND_ADJ1: return launch_kernel<PREC, CFG, 1, KIND_ADJ1>(a, P, C2, ncopy, st);
+        }
+    } else {
+        switch (kind) {
+            case KIND_PRIMAL: return launch_kernel<PREC, CFG, 2, KIND_PRIMAL>(a, P, C2, ncopy, st);
+            case KIND_TANGENT: return launch_kernel<PREC, CFG, 2, KIND_TANGENT>(a, P, C2, ncopy, st);
+            case KIND_ADJ2: return launch_kernel<PREC, CFG, 2, KIND_ADJ2>(a, P, C2, ncopy, st);
+        }
+    }
+    set_error("unsupported (stage, kind) combination");
+    return TWA_EINVAL;
+}
+
+template <int PREC>
+static int dispatch_cfg(const GemmArgs<PREC>& a, int cfg, int stage, int kind, int64_t P, int64_t C2, int ncopy,
+                        hipStream_t st) {
+    switch (cfg) {
+        case 0: return dispatch_kind<PREC, 0>(a, stage, kind, P, C2, ncopy, st);
+        case 1: return dispatch_kind<PREC, 1>(a, stage, kind, P, C2, ncopy, st);
+        case 2: return dispatch_kind<PREC, 2>(a, stage, kind, P, C2, ncopy, st);
+        case 3: return dispatch_kind<PREC, 3>(a, stage, kind, P, C2, ncopy, st);
+    }
+    if constexpr (PREC != TWA_PREC_FP64) {
+        switch (cfg) {
+            case 4: return dispatch_kind<PREC, 4>(a, stage, kind, P, C2, ncopy, st);
+            case 5: return dispatch_kind<PREC, 5>(a, stage, kind, P, C2, ncopy, st);
+            case 6: return dispatch_kind<PREC, 6>(a, stage, kind, P, C2, ncopy, st);
+        }
+    }
+    set_error("unknown tile configuration");
+    return TWA_EINVAL;
+}
+
+// forward-run contraction launches (primal or response copies)
+template <int PREC>
+static int launch_gemm_p(const Geometry& g, const EnsembleBuffers& b, const StepConsts& c, int stage,
+                         bool tangent, int cur, bool store_y2, hipStream_t st) {
     typedef typename Prec<PREC>::G G;
     typedef typename Prec<PREC>::S S;
     GemmArgs<PREC> a{};
@@ -485,6 +707,8 @@ static int launch_gemm_t(const Geometry& g, const EnsembleBuffers& b, const Step
     a.P = P;
     a.Bp = Bp;
     a.nmt = g.nmt;
+    a.N = g.N;
+    a.B = g.B;
     a.c1 = (S)c.c1;
     a.c2 = (S)c.c2;
     a.s_cur = static_cast<const S*>(b.s[cur]);
@@ -495,8 +719,7 @@ static int launch_gemm_t(const Geometry& g, const EnsembleBuffers& b, const Step
     a.g = static_cast<const S*>(b.g);
     a.store_y2 = store_y2 ? 1 : 0;
     a.step = b.step;
-    const int64_t SP3 = 3 * Bp * P;
-    a.t_state_copy = SP3;
+    a.t_state_copy = 3 * Bp * P;
     a.t_y_copy = 2 * Bp * P;
     a.t_part_copy = 3 * g.nmt * Bp;
     a.t_op_copy = g.C2 * P;
@@ -541,43 +764,7 @@ static int launch_gemm_t(const Geometry& g, const EnsembleBuffers& b, const Step
             a.ldxn = P;
         }
     }
-    // grid.x enumerates all (M tile, column tile) pairs; each block derives its tile
-    a.nnt = (int)(g.C2 / C::NT);
-    dim3 grid((unsigned)((P / C::MT) * (g.C2 / C::NT)), 1u, (unsigned)ncopy);
-    dim3 block(64 * C::WMW * C::WNW);
-    if (stage == 1) {
-        if (tangent)
-            hipLaunchKernelGGL((heun_stage_kernel<PREC, C::MT, C::NT, C::KB, C::WMW, C::WNW, C::NST, 1, true>), grid, block, 0, st, a);
-        else
-            hipLaunchKernelGGL((heun_stage_kernel<PREC, C::MT, C::NT, C::KB, C::WMW, C::WNW, C::NST, 1, false>), grid, block, 0, st, a);
-    } else {
-        if (tangent)
-            hipLaunchKernelGGL((heun_stage_kernel<PREC, C::MT, C::NT, C::KB, C::WMW, C::WNW, C::NST, 2, true>), grid, block, 0, st, a);
-        else
-            hipLaunchKernelGGL((heun_stage_kernel<PREC, C::MT, C::NT, C::KB, C::WMW, C::WNW, C::NST, 2, false>), grid, block, 0, st, a);
-    }
-    TWA_HIP_CHECK(hipGetLastError());
-    return TWA_OK;
-}
-
-template <int PREC>
-static int launch_gemm_p(const Geometry& g, const EnsembleBuffers& b, const StepConsts& c, int stage,
-                         bool tangent, int cur, bool store_y2, hipStream_t st) {
-    switch (g.cfg) {
-        case 0: return launch_gemm_t<PREC, 0>(g, b, c, stage, tangent, cur, store_y2, st);
-        case 1: return launch_gemm_t<PREC, 1>(g, b, c, stage, tangent, cur, store_y2, st);
-        case 2: return launch_gemm_t<PREC, 2>(g, b, c, stage, tangent, cur, store_y2, st);
-        case 3: return launch_gemm_t<PREC, 3>(g, b, c, stage, tangent, cur, store_y2, st);
-    }
-    if constexpr (PREC != TWA_PREC_FP64) {
-        switch (g.cfg) {
-            case 4: return launch_gemm_t<PREC, 4>(g, b, c, stage, tangent, cur, store_y2, st);
-            case 5: return launch_gemm_t<PREC, 5>(g, b, c, stage, tangent, cur, store_y2, st);
-            case 6: return launch_gemm_t<PREC, 6>(g, b, c, stage, tangent, cur, store_y2, st);
-        }
-    }
-    set_error("unknown tile configuration");
-    return TWA_EINVAL;
+    return dispatch_cfg<PREC>(a, g.cfg, stage, tangent ? KIND_TANGENT : KIND_PRIMAL, P, g.C2, ncopy, st);
 }
 
 int launch_gemm(const Geometry& g, const EnsembleBuffers& b, const StepConsts& c, int stage, bool tangent,
@@ -587,6 +774,72 @@ int launch_gemm(const Geometry& g, const EnsembleBuffers& b, const StepConsts& c
         case TWA_PREC_FP32: return launch_gemm_p<TWA_PREC_FP32>(g, b, c, stage, tangent, cur, store_y2, st);
         case TWA_PREC_BF16: return launch_gemm_p<TWA_PREC_BF16>(g, b, c, stage, tangent, cur, store_y2, st);
         case TWA_PREC_FP16: return launch_gemm_p<TWA_PREC_FP16>(g, b, c, stage, tangent, cur, store_y2, st);
+    }
+    set_error("unknown precision");
+    return TWA_EINVAL;
+}
+
+// generic launch from a type-erased call description (adjoint driver)
+template <int PREC>
+static int launch_call_p(const Geometry& g, const GemmCall& c, hipStream_t st) {
+    typedef typename Prec<PREC>::G G;
+    typedef typename Prec<PREC>::S S;
+    GemmArgs<PREC> a{};
+    a.A = static_cast<const G*>(c.A);
+    a.lda = c.lda;
+    a.X = static_cast<const G*>(c.X);
+    a.ldx = c.ldx;
+    a.x_copy = c.x_copy;
+    a.K = c.K;
+    a.P = g.P;
+    a.Bp = g.Bp;
+    a.nmt = g.nmt;
+    a.N = g.N;
+    a.B = g.B;
+    a.c1 = (S)c.c1;
+    a.c2 = (S)c.c2;
+    a.s_cur = static_cast<const S*>(c.s_cur);
+    a.s_next = static_cast<S*>(c.s_next);
+    a.dlt = static_cast<S*>(c.dlt);
+    a.Y = static_cast<S*>(c.Y);
+    a.Y2out = static_cast<S*>(c.Y2out);
+    a.Dop = static_cast<G*>(c.Dop);
+    a.Xnext = static_cast<G*>(c.Xnext);
+    a.ldxn = c.ldxn;
+    a.part_prim = static_cast<const S*>(c.part_prim);
+    a.part_out = static_cast<S*>(c.part_out);
+    a.g = static_cast<const S*>(c.g);
+    a.store_y2 = c.store_y2;
+    a.tpart_in = static_cast<const S*>(c.tpart_in);
+    a.t_state_copy = 3 * g.Bp * g.P;
+    a.t_y_copy = 2 * g.Bp * g.P;
+    a.t_part_copy = 3 * g.nmt * g.Bp;
+    a.t_op_copy = g.C2 * g.P;
+    a.step = c.step;
+    a.Sin = static_cast<const S*>(c.Sin);
+    a.Sout = static_cast<S*>(c.Sout);
+    a.store_sign = (S)c.store_sign;
+    a.Y2in = static_cast<const S*>(c.Y2in);
+    a.Qin = static_cast<const S*>(c.Qin);
+    a.YA = static_cast<const S*>(c.YA);
+    a.lam = static_cast<S*>(c.lam);
+    a.M1 = static_cast<S*>(c.M1);
+    a.Rb = static_cast<S*>(c.Rb);
+    a.gacc = c.gacc;
+    a.inv_w = (S)c.inv_w;
+    for (int q = 0; q < 2; ++q)
+        for (int m = 0; m < 5; ++m) a.srccoef[q][m] = (S)c.srccoef[q][m];
+    a.src_scale = (S)c.src_scale;
+    a.src_on = c.src_on;
+    return dispatch_cfg<PREC>(a, g.cfg, c.stage, c.kind, g.P, g.C2, c.ncopy, st);
+}
+
+int launch_gemm_call(const Geometry& g, const GemmCall& c, hipStream_t st) {
+    switch (g.precision) {
+        case TWA_PREC_FP64: return launch_call_p<TWA_PREC_FP64>(g, c, st);
+        case TWA_PREC_FP32: return launch_call_p<TWA_PREC_FP32>(g, c, st);
+        case TWA_PREC_BF16: return launch_call_p<TWA_PREC_BF16>(g, c, st);
+        case TWA_PREC_FP16: return launch_call_p<TWA_PREC_FP16>(g, c, st);
     }
     set_error("unknown precision");
     return TWA_EINVAL;
