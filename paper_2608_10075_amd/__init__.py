@@ -233,6 +233,27 @@ def run(pump: Pump, n_traj: int, dt: float, n_steps: int, seed: int = 0, *, gamm
     return res
 
 
+def run_batch(points, n_traj: int, n_steps: int, *, burnin: int = -1, gamma: float = 1.0, s0z: float = 1.0,
+              precision: str = "fp32", use_graph: bool = True, steps_per_graph: int = 16,
+              tune_cache: Optional[str] = None, stream=None):
+    """twa_run_batch: points is a sequence of (N, w, alpha, dt, seed); returns
+    one observables dict per point (Philox point index = position)."""
+    pts = (_Point * len(points))()
+    for i, (N, w, a, dt, seed) in enumerate(points):
+        pts[i].N, pts[i].w, pts[i].alpha, pts[i].dt, pts[i].seed = int(N), float(w), float(a), float(dt), int(seed)
+    o = _BatchOpts()
+    _lib.twa_batch_opts_default(C.byref(o))
+    o.n_traj, o.n_steps, o.burnin, o.gamma, o.s0z = n_traj, n_steps, burnin, gamma, s0z
+    o.precision = PRECISIONS[precision]
+    o.use_graph = 1 if use_graph else 0
+    o.steps_per_graph = steps_per_graph
+    o.tune_cache = tune_cache.encode() if tune_cache else None
+    o.stream = _stream_ptr(stream)
+    outs = (_Obs * len(points))()
+    _check(_lib.twa_run_batch(pts, len(points), C.byref(o), outs))
+    return [_obs_dict(x) for x in outs]
+
+
 GRAD_NAMES = ("d_SpSm_dw", "d_SpSm_dalpha", "d_g2_dw", "d_g2_dalpha")
 
 
@@ -280,5 +301,5 @@ def noise(seed: int, step: int, n_traj: int, N: int, point: int = 0, fp64: bool 
 
 from .autograd import TWAObservables  # noqa: E402
 
-__all__ = ["Pump", "build_pump", "run", "adjoint", "philox", "noise", "TWAError", "version", "PRECISIONS",
+__all__ = ["Pump", "build_pump", "run", "run_batch", "adjoint", "philox", "noise", "TWAError", "version", "PRECISIONS",
            "LIB_PATH", "TWAObservables"]

@@ -21,6 +21,9 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
+    # no implicit FMA contraction: the epilogue arithmetic rounds the same way in
+    # every kernel it is inlined into (single runs, grouped scans, adjoint)
+    "-ffp-contract=off",
     # packed FP32 arithmetic is disabled for all device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-result", "-I" + os.path.join(ROOT, "include"),

@@ -6,6 +6,7 @@
 #include <hip/hip_fp16.h>
 #include <stdint.h>
 #include <string>
+#include <vector>
 
 #include "../../include/twa.h"
 
@@ -122,6 +123,20 @@ struct GemmCall {
     int src_on = 0;
 };
 int launch_gemm_call(const Geometry& g, const GemmCall& c, hipStream_t st);
+
+// Grouped persistent contraction launches over many ensembles that share a
+// precision and tile configuration (one launch per stage covers all of them).
+struct GroupedPlan {
+    void* d_args[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};   // [stage-1][cur] per-ensemble arguments
+    int4* d_tiles[2] = {nullptr, nullptr};
+    int ntiles[2] = {0, 0};
+    int grid = 0, cfg = 0, precision = 0;
+    int64_t* step = nullptr;
+};
+int grouped_prepare(const std::vector<Geometry>& gs, const std::vector<EnsembleBuffers>& bs,
+                    const std::vector<StepConsts>& cs, int64_t* step, GroupedPlan& pl);
+int grouped_launch(const GroupedPlan& pl, int stage, int cur, hipStream_t st);
+void grouped_free(GroupedPlan& pl);
 
 // kernel launchers (twa_step.hip, twa_aux.hip)
 int launch_build_A(const Geometry& g, const double* W, const double* F, double dt, void* A, hipStream_t st);

@@ -19,6 +19,9 @@
 //
 // Layout: spins of one trajectory contiguous (index k * P + i), trajectory
 // operand columns interleaved x/y per 16 trajectories (see opcol).
+#include <algorithm>
+#include <vector>
+
 #include "twa_internal.h"
 #include "twa_device.h"
 
@@ -111,8 +114,10 @@ __device__ __forceinline__ void stg4(typename Prec<PREC>::G* p, const typename P
 
 // ---------------------------------------------------------------------------
 // contraction + fused Heun stage
+// One output tile (M tile mt of spins, column tile nt, copy cp) of one stage:
+// contraction over K on MFMA followed by the fused epilogue of the kind.
 template <int PREC, int MT, int NT, int KB, int WMW, int WNW, int NST, int STAGE, int KIND>
-__global__ __launch_bounds__(64 * WMW * WNW) void heun_stage_kernel(GemmArgs<PREC> a) {
+__device__ __forceinline__ void stage_tile(const GemmArgs<PREC>& a, const int mt, const int nt, const int cp) {
     constexpr bool TAN = KIND == KIND_TANGENT;
     constexpr bool ADJ = KIND == KIND_ADJ2 || KIND == KIND_ADJ1;
     constexpr bool TCOPY = TAN || ADJ;     // per-copy collective sums of the copy operand
@@ -151,21 +156,6 @@ __global__ __launch_bounds__(64 * WMW * WNW) void heun_stage_kernel(GemmArgs<PRE
     __shared__ S red[WMW][NTRJ][4];
     __shared__ S sSrc[NTRJ][3];    // adjoint: observation source of each trajectory
 
-    // XCD-aware tile order: workgroups are dispatched round-robin over the 8
-    // XCDs, so workgroup b runs on XCD b % 8.  Each XCD is given a contiguous
-    // range of tiles ordered M-tile-major, so the workgroups resident on one
-    // XCD share the same rows of A (and walk K together) in that XCD's L2.
-    int mt, nt;
-    {
-        const int nnt = a.nnt;            // column tiles
-        const int T = (int)gridDim.x;     // total tiles = nmt * nnt
-        const int q = T / 8, r = T % 8;
-        const int b = (int)blockIdx.x, x = b % 8, j = b / 8;
-        const int L = x * q + (x < r ? x : r) + j;
-        mt = L / nnt;
-        nt = L % nnt;
-    }
-    const int cp = blockIdx.z;
     const int64_t m0 = (int64_t)mt * MT, n0 = (int64_t)nt * NT;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave % WMW, wn = wave / WMW;
@@ -606,8 +596,41 @@ __global__ __launch_bounds__(64 * WMW * WNW) void heun_stage_kernel(GemmArgs<PRE
             }
         }
     }
+}
+
+// One launch = one stage of one ensemble.  XCD-aware tile order: workgroups
+// are dispatched round-robin over the 8 XCDs, so workgroup b runs on XCD b % 8.
+// Each XCD is given a contiguous range of tiles ordered M-tile-major, so the
+// workgroups resident on one XCD share the same rows of A (and walk K
+// together) in that XCD's L2.
+template <int PREC, int MT, int NT, int KB, int WMW, int WNW, int NST, int STAGE, int KIND>
+__global__ __launch_bounds__(64 * WMW * WNW) void heun_stage_kernel(GemmArgs<PREC> a) {
+    const int nnt = a.nnt;            // column tiles
+    const int T = (int)gridDim.x;     // total tiles = nmt * nnt
+    const int q = T / 8, r = T % 8;
+    const int b = (int)blockIdx.x, x = b % 8, j = b / 8;
+    const int L = x * q + (x < r ? x : r) + j;
+    stage_tile<PREC, MT, NT, KB, WMW, WNW, NST, STAGE, KIND>(a, L / nnt, L % nnt, (int)blockIdx.z);
     if constexpr (KIND == KIND_PRIMAL && STAGE == 2) {
-        if (blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && tid == 0) a.step[0] += 1;
+        if (blockIdx.x == 0 && blockIdx.z == 0 && threadIdx.x == 0) a.step[0] += 1;
+    }
+}
+
+// Grouped persistent launch: the stage of many independent ensembles (the
+// points of a parameter scan), each with its own arguments, over one tile
+// list (point, M tile, column tile, copy) ordered longest-first; workgroup b
+// takes tiles b, b + grid, b + 2 grid, ...
+template <int PREC, int MT, int NT, int KB, int WMW, int WNW, int NST, int STAGE, int KIND>
+__global__ __launch_bounds__(64 * WMW * WNW) void heun_stage_grouped(const GemmArgs<PREC>* __restrict__ args,
+                                                                     const int4* __restrict__ tiles, int ntiles,
+                                                                     int64_t* step) {
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int4 tt = tiles[t];
+        __syncthreads();   // LDS of the previous tile is free
+        stage_tile<PREC, MT, NT, KB, WMW, WNW, NST, STAGE, KIND>(args[tt.x], tt.y, tt.z, tt.w);
+    }
+    if constexpr (KIND == KIND_PRIMAL && STAGE == 2) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) step[0] += 1;
     }
 }
 
@@ -694,10 +717,10 @@ static int dispatch_cfg(const GemmArgs<PREC>& a, int cfg, int stage, int kind, i
     return TWA_EINVAL;
 }
 
-// forward-run contraction launches (primal or response copies)
+// arguments of a forward-run contraction launch (primal or response copies)
 template <int PREC>
-static int launch_gemm_p(const Geometry& g, const EnsembleBuffers& b, const StepConsts& c, int stage,
-                         bool tangent, int cur, bool store_y2, hipStream_t st) {
+static GemmArgs<PREC> make_args(const Geometry& g, const EnsembleBuffers& b, const StepConsts& c, int stage,
+                                bool tangent, int cur, bool store_y2) {
     typedef typename Prec<PREC>::G G;
     typedef typename Prec<PREC>::S S;
     GemmArgs<PREC> a{};
@@ -723,7 +746,6 @@ static int launch_gemm_p(const Geometry& g, const EnsembleBuffers& b, const Step
     a.t_y_copy = 2 * Bp * P;
     a.t_part_copy = 3 * g.nmt * Bp;
     a.t_op_copy = g.C2 * P;
-    int ncopy = 1;
     if (!tangent) {
         if (stage == 1) {
             a.X = static_cast<const G*>(b.Xop);
@@ -741,7 +763,6 @@ static int launch_gemm_p(const Geometry& g, const EnsembleBuffers& b, const Step
             a.ldxn = 2 * P;
         }
     } else {
-        ncopy = 2;
         a.t_cur = static_cast<const S*>(b.ts[cur]);
         a.t_next = static_cast<S*>(b.ts[1 - cur]);
         a.t_dlt = static_cast<S*>(b.tdlt);
@@ -764,7 +785,15 @@ static int launch_gemm_p(const Geometry& g, const EnsembleBuffers& b, const Step
             a.ldxn = P;
         }
     }
-    return dispatch_cfg<PREC>(a, g.cfg, stage, tangent ? KIND_TANGENT : KIND_PRIMAL, P, g.C2, ncopy, st);
+    return a;
+}
+
+template <int PREC>
+static int launch_gemm_p(const Geometry& g, const EnsembleBuffers& b, const StepConsts& c, int stage,
+                         bool tangent, int cur, bool store_y2, hipStream_t st) {
+    const GemmArgs<PREC> a = make_args<PREC>(g, b, c, stage, tangent, cur, store_y2);
+    return dispatch_cfg<PREC>(a, g.cfg, stage, tangent ? KIND_TANGENT : KIND_PRIMAL, g.P, g.C2, tangent ? 2 : 1,
+                              st);
 }
 
 int launch_gemm(const Geometry& g, const EnsembleBuffers& b, const StepConsts& c, int stage, bool tangent,
@@ -843,6 +872,147 @@ int launch_gemm_call(const Geometry& g, const GemmCall& c, hipStream_t st) {
     }
     set_error("unknown precision");
     return TWA_EINVAL;
+}
+
+
+// ---------------------------------------------------------------------------
+// grouped persistent launches of many ensembles (batched parameter scan)
+template <int PREC, int CFG, int STAGE>
+static int grouped_launch_t(const GroupedPlan& pl, int cur, hipStream_t st) {
+    typedef CfgT<PREC, CFG> C;
+    hipLaunchKernelGGL((heun_stage_grouped<PREC, C::MT, C::NT, C::KB, C::WMW, C::WNW, C::NST, STAGE, KIND_PRIMAL>),
+                       dim3((unsigned)pl.grid), dim3(64 * C::WMW * C::WNW), 0, st,
+                       static_cast<const GemmArgs<PREC>*>(pl.d_args[STAGE - 1][cur]), pl.d_tiles[STAGE - 1],
+                       pl.ntiles[STAGE - 1], pl.step);
+    TWA_HIP_CHECK(hipGetLastError());
+    return TWA_OK;
+}
+
+template <int PREC, int CFG>
+static int grouped_occupancy(int stage) {
+    typedef CfgT<PREC, CFG> C;
+    int nb = 0;
+    if (stage == 1)
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &nb, heun_stage_grouped<PREC, C::MT, C::NT, C::KB, C::WMW, C::WNW, C::NST, 1, KIND_PRIMAL>,
+            64 * C::WMW * C::WNW, 0);
+    else
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &nb, heun_stage_grouped<PREC, C::MT, C::NT, C::KB, C::WMW, C::WNW, C::NST, 2, KIND_PRIMAL>,
+            64 * C::WMW * C::WNW, 0);
+    return nb > 0 ? nb : 1;
+}
+
+template <int PREC, int CFG>
+static int grouped_dispatch(const GroupedPlan& pl, int stage, int cur, hipStream_t st) {
+    return stage == 1 ? grouped_launch_t<PREC, CFG, 1>(pl, cur, st) : grouped_launch_t<PREC, CFG, 2>(pl, cur, st);
+}
+
+template <int PREC>
+static int grouped_prepare_p(const std::vector<Geometry>& gs, const std::vector<EnsembleBuffers>& bs,
+                             const std::vector<StepConsts>& cs, int64_t* step, GroupedPlan& pl) {
+    const int np = (int)gs.size();
+    const int cfg = gs[0].cfg;
+    const TileCfg& tc = tile_cfg(cfg);
+    for (int stage = 1; stage <= 2; ++stage)
+        for (int cur = 0; cur < 2; ++cur) {
+            std::vector<GemmArgs<PREC>> h((size_t)np);
+            for (int p = 0; p < np; ++p) {
+                h[(size_t)p] = make_args<PREC>(gs[(size_t)p], bs[(size_t)p], cs[(size_t)p], stage, false, cur, false);
+                h[(size_t)p].nnt = (int)(gs[(size_t)p].C2 / tc.nt);
+            }
+            TWA_HIP_CHECK(hipMalloc(&pl.d_args[stage - 1][cur], h.size() * sizeof(GemmArgs<PREC>)));
+            TWA_HIP_CHECK(hipMemcpy(pl.d_args[stage - 1][cur], h.data(), h.size() * sizeof(GemmArgs<PREC>),
+                                    hipMemcpyHostToDevice));
+        }
+    int dev = 0, ncu = 0;
+    TWA_HIP_CHECK(hipGetDevice(&dev));
+    TWA_HIP_CHECK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    int occ = 1;
+    switch (cfg) {
+        case 0: occ = grouped_occupancy<PREC, 0>(1); break;
+        case 1: occ = grouped_occupancy<PREC, 1>(1); break;
+        case 2: occ = grouped_occupancy<PREC, 2>(1); break;
+        case 3: occ = grouped_occupancy<PREC, 3>(1); break;
+        default: break;
+    }
+    // tile list: (point, M tile, column tile, 0), longest contraction first
+    std::vector<int4> tiles;
+    std::vector<int> order((size_t)np);
+    for (int p = 0; p < np; ++p) order[(size_t)p] = p;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return gs[(size_t)x].P > gs[(size_t)y].P; });
+    for (int p : order) {
+        const Geometry& g = gs[(size_t)p];
+        const int nnt = (int)(g.C2 / tc.nt);
+        for (int mt = 0; mt < (int)g.nmt; ++mt)
+            for (int nt = 0; nt < nnt; ++nt) tiles.push_back(make_int4(p, mt, nt, 0));
+    }
+    const int ntl = (int)tiles.size();
+    int grid = std::min(ncu * occ, ntl);
+    grid = std::max(1, grid);
+    // within every full round of `grid` tiles, give XCD x (workgroups w with
+    // w % 8 == x) a contiguous block of the list
+    if (grid % 8 == 0) {
+        std::vector<int4> perm(tiles);
+        const int per = grid / 8;
+        for (int r0 = 0; r0 + grid <= ntl; r0 += grid)
+            for (int w = 0; w < grid; ++w) perm[(size_t)(r0 + w)] = tiles[(size_t)(r0 + (w % 8) * per + w / 8)];
+        tiles.swap(perm);
+    }
+    for (int stage = 0; stage < 2; ++stage) {
+        TWA_HIP_CHECK(hipMalloc((void**)&pl.d_tiles[stage], tiles.size() * sizeof(int4)));
+        TWA_HIP_CHECK(hipMemcpy(pl.d_tiles[stage], tiles.data(), tiles.size() * sizeof(int4), hipMemcpyHostToDevice));
+        pl.ntiles[stage] = ntl;
+    }
+    pl.grid = grid;
+    pl.cfg = cfg;
+    pl.precision = PREC;
+    pl.step = step;
+    return TWA_OK;
+}
+
+int grouped_prepare(const std::vector<Geometry>& gs, const std::vector<EnsembleBuffers>& bs,
+                    const std::vector<StepConsts>& cs, int64_t* step, GroupedPlan& pl) {
+    if (gs.empty()) return TWA_EINVAL;
+    switch (gs[0].precision) {
+        case TWA_PREC_FP32: return grouped_prepare_p<TWA_PREC_FP32>(gs, bs, cs, step, pl);
+        case TWA_PREC_BF16: return grouped_prepare_p<TWA_PREC_BF16>(gs, bs, cs, step, pl);
+        case TWA_PREC_FP16: return grouped_prepare_p<TWA_PREC_FP16>(gs, bs, cs, step, pl);
+        case TWA_PREC_FP64: return grouped_prepare_p<TWA_PREC_FP64>(gs, bs, cs, step, pl);
+    }
+    set_error("unknown precision");
+    return TWA_EINVAL;
+}
+
+template <int PREC>
+static int grouped_launch_p(const GroupedPlan& pl, int stage, int cur, hipStream_t st) {
+    switch (pl.cfg) {
+        case 0: return grouped_dispatch<PREC, 0>(pl, stage, cur, st);
+        case 1: return grouped_dispatch<PREC, 1>(pl, stage, cur, st);
+        case 2: return grouped_dispatch<PREC, 2>(pl, stage, cur, st);
+        case 3: return grouped_dispatch<PREC, 3>(pl, stage, cur, st);
+    }
+    set_error("grouped launch: tile configuration must be 0..3");
+    return TWA_EINVAL;
+}
+
+int grouped_launch(const GroupedPlan& pl, int stage, int cur, hipStream_t st) {
+    switch (pl.precision) {
+        case TWA_PREC_FP32: return grouped_launch_p<TWA_PREC_FP32>(pl, stage, cur, st);
+        case TWA_PREC_BF16: return grouped_launch_p<TWA_PREC_BF16>(pl, stage, cur, st);
+        case TWA_PREC_FP16: return grouped_launch_p<TWA_PREC_FP16>(pl, stage, cur, st);
+        case TWA_PREC_FP64: return grouped_launch_p<TWA_PREC_FP64>(pl, stage, cur, st);
+    }
+    set_error("unknown precision");
+    return TWA_EINVAL;
+}
+
+void grouped_free(GroupedPlan& pl) {
+    for (int s = 0; s < 2; ++s) {
+        for (int c = 0; c < 2; ++c) hipFree(pl.d_args[s][c]);
+        hipFree(pl.d_tiles[s]);
+    }
+    pl = GroupedPlan();
 }
 
 }  // namespace twa
