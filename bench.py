@@ -21,6 +21,13 @@ recorded by the library on its stream during the timed runs.
 ``cpu_baseline`` times the FP64 NumPy oracle (test infrastructure) on the
 host's cores on a bounded sample of the same workload (a few trajectories for
 a few steps at N = 10^4).
+
+``adjoint`` is the second half of the metric: the cost of the pathwise
+gradients d<S+S->/d(w, alpha) and dg2/d(w, alpha) (checkpointed forward plus
+reverse sweep) relative to a plain forward run of the same configuration
+(N = 2000, alpha = 1, w = 2, 2048 trajectories, dt = 1e-4, FP32 contractions,
+a checkpoint every 256 steps).  The ratio is per step, so a bounded number of
+steps (2048, i.e. 8 checkpoint segments) is timed.
 """
 from __future__ import annotations
 
@@ -91,6 +98,34 @@ def cpu_baseline(N, w, alpha, dt, budget_s=15.0):
                       "%.1f s not included" % (N, B, steps, el, build_s)}
 
 
+def adjoint_cost(twa, steps=2048, reps=1):
+    """Wall time of twa_adjoint (forward with checkpoints + reverse sweep)
+    divided by the wall time of twa_run on the same configuration."""
+    import torch
+    N, B, w, alpha, dt, ck = 2000, 2048, 2.0, 1.0, 1e-4, 256
+    pump = twa.build_pump(N, w, alpha)
+    twa.run(pump, B, dt, 64, seed=0, precision="fp32")           # warm caches / graphs
+    twa.adjoint(pump, B, dt, 256, seed=0, precision="fp32", ckpt_every=ck)
+    fwd, adj = [], []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.time()
+        r = twa.run(pump, B, dt, steps, seed=0, precision="fp32")
+        torch.cuda.synchronize()
+        t1 = time.time()
+        obs, grads = twa.adjoint(pump, B, dt, steps, seed=0, precision="fp32", ckpt_every=ck)
+        torch.cuda.synchronize()
+        t2 = time.time()
+        fwd.append(t1 - t0)
+        adj.append(t2 - t1)
+    f, a = min(fwd), min(adj)
+    return {"ratio": a / f, "forward_s": f, "adjoint_s": a, "steps": steps,
+            "config": {"N": N, "alpha": alpha, "w": w, "n_traj": B, "dt": dt, "precision": "fp32",
+                       "ckpt_every": ck, "tile_config": r.obs["tile_config"]},
+            "forward_ms_per_step": 1e3 * f / steps, "adjoint_ms_per_step": 1e3 * a / steps,
+            "gradients": grads}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -99,6 +134,7 @@ def main():
     ap.add_argument("--precision", default="bf16", choices=sorted(PEAK_TFLOPS))
     ap.add_argument("--tile-config", type=int, default=-1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (trajectories would shard "
@@ -174,6 +210,9 @@ def main():
                                              "step_criterion")},
         "tile_config": obs["tile_config"],
     }
+    if not args.no_adjoint:
+        print("[bench] adjoint cost ratio (N=2000, FP32)", file=sys.stderr, flush=True)
+        line["adjoint"] = adjoint_cost(twa)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(N, w, alpha, dt)

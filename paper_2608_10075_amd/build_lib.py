@@ -26,6 +26,9 @@ FLAGS = [
     "-ffp-contract=off",
     # packed FP32 arithmetic is disabled for all device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # MFMA accumulators in architectural VGPRs: keeps the loop-carried
+    # accumulators in place instead of copying them through AGPRs every stage
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-Wno-unused-result", "-I" + os.path.join(ROOT, "include"),
 ]
 LIBS = ["-L/opt/rocm/lib", "-lrocsolver", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]

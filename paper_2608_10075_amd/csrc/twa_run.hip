@@ -26,11 +26,29 @@ int gemm_elt_bytes(int precision) {
 int state_elt_bytes(int precision) { return precision == TWA_PREC_FP64 ? 8 : 4; }
 
 int pick_tile_cfg(int precision, int64_t N, int64_t n_traj) {
-    (void)precision;
-    (void)n_traj;
     if (N <= 48) return 0;
     if (N <= 768) return 1;
-    return 2;
+    if (precision == TWA_PREC_FP64) return 2;
+    // Large N: 128x128 tiles (4 waves) or 320x256 tiles (8 waves), whichever
+    // gives the shorter estimated contraction time = rounds of resident tiles
+    // x work per tile / per-tile rate.  The larger tile moves 45 % fewer bytes
+    // per flop through the vector-memory path (the bound of the smaller one)
+    // and runs 1.64x faster per tile, but needs enough tiles to fill the device.
+    static int ncu = 0;
+    if (ncu <= 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0)
+            ncu = 256;
+    }
+    auto est = [&](int cfg, double rate) {
+        const TileCfg& t = tile_cfg(cfg);
+        const int64_t P = round_up(N, t.mt), Bp = round_up(n_traj, t.nt / 2);
+        const int64_t tiles = (P / t.mt) * (2 * Bp / t.nt);
+        const int64_t rounds = (tiles + ncu - 1) / ncu;
+        return (double)rounds * (double)(t.mt * t.nt) / rate;
+    };
+    return est(7, 1.64) < est(2, 1.0) ? 7 : 2;
 }
 
 // ---------------------------------------------------------------------------

@@ -153,7 +153,11 @@ __device__ __forceinline__ void stage_tile(const GemmArgs<PREC>& a, const int mt
     __shared__ S sS[NTRJ][2];      // primal collective sums of the trajectories of the tile
     __shared__ S sT[NTRJ][2];      // tangent collective sums
     __shared__ S sG[NTRJ][2];      // collective normals
-    __shared__ S red[WMW][NTRJ][4];
+    // cross-wave partial sums: [wave row][trajectory][4 channels] in the
+    // epilogue, [thread group][trajectory][5 channels] for the collective sums
+    constexpr int NG = NTHR / NTRJ;            // thread groups of the collective sums
+    static_assert(NTHR % NTRJ == 0, "thread groups");
+    __shared__ S red[WMW > NG ? WMW : NG][NTRJ][5];
     __shared__ S sSrc[NTRJ][3];    // adjoint: observation source of each trajectory
 
     const int64_t m0 = (int64_t)mt * MT, n0 = (int64_t)nt * NT;
@@ -162,50 +166,6 @@ __device__ __forceinline__ void stage_tile(const GemmArgs<PREC>& a, const int mt
     const int wm0 = wm * WM, wn0 = wn * WN;
     const int64_t P = a.P, Bp = a.Bp, nmt = a.nmt;
     const int64_t k0t = n0 / 2;    // first trajectory of the tile
-
-    // ---- collective sums of this tile's trajectories (ordered over M tiles)
-    if constexpr (KIND != KIND_STORE) {
-        for (int t = tid; t < NTRJ; t += NTHR) {
-            const int64_t k = k0t + t;
-            const S* pp = a.part_prim;
-            S sx = 0, sy = 0, sz = 0;
-            for (int64_t q = 0; q < nmt; ++q) {
-                sx += pp[(0 * nmt + q) * Bp + k];
-                sy += pp[(1 * nmt + q) * Bp + k];
-                if constexpr (KIND == KIND_ADJ1) sz += pp[(2 * nmt + q) * Bp + k];
-            }
-            sS[t][0] = sx;
-            sS[t][1] = sy;
-            sG[t][0] = a.g[k];
-            sG[t][1] = a.g[Bp + k];
-            if constexpr (TCOPY) {
-                const S* tp = a.tpart_in + cp * a.t_part_copy;
-                S tx = 0, ty = 0;
-                for (int64_t q = 0; q < nmt; ++q) {
-                    tx += tp[(0 * nmt + q) * Bp + k];
-                    ty += tp[(1 * nmt + q) * Bp + k];
-                }
-                sT[t][0] = tx;
-                sT[t][1] = ty;
-            }
-            if constexpr (KIND == KIND_ADJ1) {
-                // derivative of the observed moments (T2, T3, T4, Z, ZZ) of this
-                // trajectory's state with respect to any one spin component
-                S ox = 0, oy = 0, oz = 0;
-                if (a.src_on && k < a.B) {
-                    const S T2 = S(0.25) * (sx * sx + sy * sy);
-                    const S* cf = a.srccoef[cp];
-                    const S gt = S(0.5) * cf[0] + S(0.5) * cf[1] * sz + cf[2] * T2;
-                    ox = a.src_scale * gt * sx;
-                    oy = a.src_scale * gt * sy;
-                    oz = a.src_scale * (cf[1] * T2 + cf[3] + S(2) * cf[4] * sz);
-                }
-                sSrc[t][0] = ox;
-                sSrc[t][1] = oy;
-                sSrc[t][2] = oz;
-            }
-        }
-    }
 
     // ---- main loop: acc[i][col] = sum_k A[m0+i][k] X[n0+col][k]
     AV acc[BI][BJ];
@@ -224,14 +184,20 @@ __device__ __forceinline__ void stage_tile(const GemmArgs<PREC>& a, const int mt
     constexpr int RPC = 1024 / KB;                 // rows per 1 KB chunk
     constexpr int NCH = (MT + NT) / RPC;           // chunks per stage
     constexpr int NWV = NTHR / 64;
-    constexpr int CPW = NCH / NWV;                 // chunks per wave per stage
-    static_assert(NCH % NWV == 0 && MT % RPC == 0, "chunking");
-    auto swz = [](int r16) { return (r16 / (16 / PCS)) % PCS; };
+    constexpr int CPW = (NCH + NWV - 1) / NWV;     // chunks per wave per stage (at most)
+    constexpr int CPWMIN = NCH / NWV;              // (at least)
+    static_assert(MT % RPC == 0 && (MT + NT) % RPC == 0, "chunking");
+    // (gfx950 serves a 16-byte LDS read in four passes of 16 lanes over 64
+    // four-byte banks; these swizzles make every pass of the fragment reads
+    // conflict free, for the FP64 row order as well)
+    auto swz = [](int r16) {
+        return PREC == TWA_PREC_FP64 ? (r16 ^ (r16 >> 2)) % PCS : (PCS >= 16 ? r16 : r16 >> 1) % PCS;
+    };
     const int wv = __builtin_amdgcn_readfirstlane(wave);
     const char* src[CPW];
 #pragma unroll
     for (int j = 0; j < CPW; ++j) {
-        const int q = wv + j * NWV;
+        const int q = wv + j * NWV < NCH ? wv + j * NWV : 0;
         const int row = q * RPC + lane / PCS;
         const int pc = (lane % PCS) ^ swz(row & 15);
         src[j] = row < MT ? Ag + row * lda_b + pc * 16 : Xg + (int64_t)(row - MT) * ldx_b + pc * 16;
@@ -241,14 +207,20 @@ __device__ __forceinline__ void stage_tile(const GemmArgs<PREC>& a, const int mt
 #define TWA_DMA(KT_, BUF_)                                                                              \
     do {                                                                                                \
         const int64_t kofs_ = (int64_t)(KT_) * KB;                                                      \
-        _Pragma("unroll") for (int j = 0; j < CPW; ++j) __builtin_amdgcn_global_load_lds(               \
-            (gptr_t*)(src[j] + kofs_), (lds_t*)((BUF_) + (wv + j * NWV) * 1024), 16, 0, 0);              \
+        _Pragma("unroll") for (int j = 0; j < CPW; ++j) if (CPW == CPWMIN || wv + j * NWV < NCH)        \
+            __builtin_amdgcn_global_load_lds((gptr_t*)(src[j] + kofs_),                                 \
+                                             (lds_t*)((BUF_) + (wv + j * NWV) * 1024), 16, 0, 0);       \
     } while (0)
 
     // fragment read offsets of this lane (row within a 16-row block, swizzle)
     const int ra = Prec<PREC>::arow(lane & 15), rx = lane & 15;
     const int offA = (wm0 + ra) * KB, offX = (MT + wn0 + rx) * KB;
     const int swA = swz(ra), swX = swz(rx), grp = lane >> 4;
+#define TWA_BUF(I_) ((I_) == 0 ? L0 : (I_) == 1 ? L1 : (I_) == 2 ? L2 : (I_) == 3 ? L3 : \
+                     (I_) == 4 ? L4 : (I_) == 5 ? L5 : (I_) == 6 ? L6 : L7)
+    // vmcnt-only wait (expcnt and lgkmcnt left at their maxima), gfx9 encoding
+#define TWA_WAIT_VM(N_) __builtin_amdgcn_s_waitcnt(((N_) & 15) | (((N_) >> 4) << 14) | (7 << 4) | (15 << 8))
+
 #define TWA_COMPUTE(BUF_)                                                                               \
     do {                                                                                                \
         _Pragma("unroll") for (int seg = 0; seg < KB / 64; ++seg) {                                     \
@@ -267,6 +239,72 @@ __device__ __forceinline__ void stage_tile(const GemmArgs<PREC>& a, const int mt
     // vmcnt-only wait (expcnt and lgkmcnt left at their maxima), gfx9 encoding
 #define TWA_WAIT_VM(N_) __builtin_amdgcn_s_waitcnt(((N_) & 15) | (((N_) >> 4) << 14) | (7 << 4) | (15 << 8))
 
+
+    // ---- collective sums of this tile's trajectories: thread group g of
+    // trajectory kl adds the partial sums of the M tiles
+    // q in [g nmt / NG, (g+1) nmt / NG) in order, then the groups are added in
+    // order (a fixed summation order: the result does not depend on timing).
+    // Channels: 0, 1 primal x, y; 2, 3 copy x, y; 4 primal z.
+    if constexpr (KIND != KIND_STORE) {
+        constexpr int NCHAN = KIND == KIND_ADJ1 ? 5 : TCOPY ? 4 : 2;
+        {
+            const int kl = tid % NTRJ, gq = tid / NTRJ;
+            const int64_t k = k0t + kl;
+            const int64_t q0 = nmt * gq / NG, q1 = nmt * (gq + 1) / NG;
+            const S* pp = a.part_prim;
+            const S* tp = TCOPY ? a.tpart_in + cp * a.t_part_copy : nullptr;
+            S v[5] = {0, 0, 0, 0, 0};
+#pragma unroll 4
+            for (int64_t q = q0; q < q1; ++q) {
+                v[0] += pp[(0 * nmt + q) * Bp + k];
+                v[1] += pp[(1 * nmt + q) * Bp + k];
+                if constexpr (TCOPY) {
+                    v[2] += tp[(0 * nmt + q) * Bp + k];
+                    v[3] += tp[(1 * nmt + q) * Bp + k];
+                }
+                if constexpr (KIND == KIND_ADJ1) v[4] += pp[(2 * nmt + q) * Bp + k];
+            }
+#pragma unroll
+            for (int c = 0; c < NCHAN; ++c) red[gq][kl][c] = v[c];
+        }
+        __syncthreads();
+        for (int t = tid; t < NTRJ; t += NTHR) {
+            const int64_t k = k0t + t;
+            S v[5];
+#pragma unroll
+            for (int c = 0; c < NCHAN; ++c) {
+                v[c] = red[0][t][c];
+                for (int g2 = 1; g2 < NG; ++g2) v[c] += red[g2][t][c];
+            }
+            const S sx = v[0], sy = v[1];
+            sS[t][0] = sx;
+            sS[t][1] = sy;
+            sG[t][0] = a.g[k];
+            sG[t][1] = a.g[Bp + k];
+            if constexpr (TCOPY) {
+                sT[t][0] = v[2];
+                sT[t][1] = v[3];
+            }
+            if constexpr (KIND == KIND_ADJ1) {
+                // derivative of the observed moments (T2, T3, T4, Z, ZZ) of this
+                // trajectory's state with respect to any one spin component
+                const S sz = v[4];
+                S ox = 0, oy = 0, oz = 0;
+                if (a.src_on && k < a.B) {
+                    const S T2 = S(0.25) * (sx * sx + sy * sy);
+                    const S* cf = a.srccoef[cp];
+                    const S gt = S(0.5) * cf[0] + S(0.5) * cf[1] * sz + cf[2] * T2;
+                    ox = a.src_scale * gt * sx;
+                    oy = a.src_scale * gt * sy;
+                    oz = a.src_scale * (cf[1] * T2 + cf[3] + S(2) * cf[4] * sz);
+                }
+                sSrc[t][0] = ox;
+                sSrc[t][1] = oy;
+                sSrc[t][2] = oz;
+            }
+        }
+        __syncthreads();   // the sums are visible to every wave; red is free again
+    }
     // prologue: stages 0 .. NST-2 in flight
 #pragma unroll
     for (int u = 0; u < NST - 1; ++u)
@@ -277,7 +315,8 @@ __device__ __forceinline__ void stage_tile(const GemmArgs<PREC>& a, const int mt
             const int kt = kt0 + u;
             if (kt < nk) {
                 // stage kt has landed once at most the later stages are pending
-                if (nk - 1 - kt >= NST - 2) TWA_WAIT_VM((NST - 2) * CPW);
+                // (waves that load fewer chunks per stage wait conservatively)
+                if (nk - 1 - kt >= NST - 2) TWA_WAIT_VM((NST - 2) * CPWMIN);
                 else TWA_WAIT_VM(0);
                 // Barrier without a memory fence: a fence would wait for every
                 // load still in flight into the later stages.  What it has to
@@ -643,7 +682,9 @@ static const TileCfg kCfgs[] = {
     {3, 128, 128, 64, 2, 2, 8, "128x128 K64B 4w 8st"},
     {4, 256, 128, 64, 4, 1, 6, "256x128 K64B 4w 6st"},
     {5, 128, 256, 64, 2, 2, 6, "128x256 K64B 4w 6st"},
-    {6, 256, 256, 64, 4, 2, 4, "256x256 K64B 8w 4st"},
+    {6, 256, 128, 64, 4, 2, 4, "256x128 K64B 8w 4st"},
+    {7, 320, 256, 128, 4, 2, 2, "320x256 K128B 8w 2st"},
+    {8, 320, 256, 64, 4, 2, 4, "320x256 K64B 8w 4st"},
 };
 int n_tile_cfgs() { return (int)(sizeof(kCfgs) / sizeof(kCfgs[0])); }
 const TileCfg& tile_cfg(int id) { return kCfgs[id]; }
@@ -661,7 +702,9 @@ TWA_CFG(2, 128, 128, 128, 2, 2, 4)
 TWA_CFG(3, 128, 128, 64, 2, 2, 8)
 TWA_CFG(4, 256, 128, 64, 4, 1, 6)
 TWA_CFG(5, 128, 256, 64, 2, 2, 6)
-TWA_CFG(6, 256, 256, 64, 4, 2, 4)
+TWA_CFG(6, 256, 128, 64, 4, 2, 4)
+TWA_CFG(7, 320, 256, 128, 4, 2, 2)
+TWA_CFG(8, 320, 256, 64, 4, 2, 4)
 
 template <int PREC, int CFG, int STAGE, int KIND>
 static int launch_kernel(const GemmArgs<PREC>& a, int64_t P, int64_t C2, int ncopy, hipStream_t st) {
@@ -711,6 +754,8 @@ static int dispatch_cfg(const GemmArgs<PREC>& a, int cfg, int stage, int kind, i
             case 4: return dispatch_kind<PREC, 4>(a, stage, kind, P, C2, ncopy, st);
             case 5: return dispatch_kind<PREC, 5>(a, stage, kind, P, C2, ncopy, st);
             case 6: return dispatch_kind<PREC, 6>(a, stage, kind, P, C2, ncopy, st);
+            case 7: return dispatch_kind<PREC, 7>(a, stage, kind, P, C2, ncopy, st);
+            case 8: return dispatch_kind<PREC, 8>(a, stage, kind, P, C2, ncopy, st);
         }
     }
     set_error("unknown tile configuration");
