@@ -66,14 +66,14 @@ def pathwise_gradients(cfg: RunConfig):
     dF = {"w": p.F / (2.0 * cfg.w), "alpha": dfactor(p, dW["alpha"])}
     B, n = cfg.n_traj, cfg.n_spin
     burn = cfg.resolved_burnin()
-    state = initial_state(cfg.seed, B, n, cfg.s0z, cfg.point)
+    state = initial_state(cfg.seed, B, n, cfg.s0z, cfg.point, cfg.traj)
     tang = {k: tuple(np.zeros((B, n)) for _ in range(3)) for k in dW}
     acc = np.zeros((B, 5))
     dacc = {k: np.zeros((B, 5)) for k in dW}
     ns = 0
     for step in range(cfg.n_steps):
-        g = philox.collective_noise(cfg.seed, step, B, cfg.point)
-        zeta = philox.pump_noise(cfg.seed, step, B, n, cfg.point)
+        g = philox.collective_noise(cfg.seed, step, B, cfg.point, cfg.traj)
+        zeta = philox.pump_noise(cfg.seed, step, B, n, cfg.point, cfg.traj)
         d1, _ = _incr(state, p.W, p.F, cfg.gamma, cfg.dt, g, zeta)
         pred = tuple(s + d for s, d in zip(state, d1))
         d2, _ = _incr(pred, p.W, p.F, cfg.gamma, cfg.dt, g, zeta)

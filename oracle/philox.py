@@ -78,12 +78,23 @@ def _tagword(tag: int, point: int):
     return np.uint64((tag | (int(point) << 8)) & 0xFFFFFFFF)
 
 
-def pump_noise(seed: int, step: int, n_traj: int, n_spin: int, point: int = 0):
-    """Standard normals zeta^x, zeta^y of shape (n_traj, n_spin) for one step."""
+def _traj_index(n_traj: int, traj):
+    """Trajectory counters: 0 .. n_traj-1, or the given trajectory indices."""
+    if traj is None:
+        return np.arange(n_traj, dtype=np.uint64)
+    t = np.asarray(traj, dtype=np.uint64).reshape(-1)
+    if t.shape[0] != n_traj:
+        raise ValueError("traj must list n_traj trajectory indices")
+    return t
+
+
+def pump_noise(seed: int, step: int, n_traj: int, n_spin: int, point: int = 0, traj=None):
+    """Standard normals zeta^x, zeta^y of shape (n_traj, n_spin) for one step
+    (of trajectories 0 .. n_traj-1, or of the trajectory indices ``traj``)."""
     k0, k1 = seed_key(seed)
     n_slot = (n_spin + 1) // 2
     m = np.arange(n_slot, dtype=np.uint64)[None, :]
-    k = np.arange(n_traj, dtype=np.uint64)[:, None]
+    k = _traj_index(n_traj, traj)[:, None]
     x0, x1, x2, x3 = philox4x32_10(m, k, np.uint64(step), _tagword(TAG_PUMP, point), k0, k1)
     za, zb = box_muller(x0, x1)   # spin 2m: (x, y)
     zc, zd = box_muller(x2, x3)   # spin 2m+1: (x, y)
@@ -94,20 +105,20 @@ def pump_noise(seed: int, step: int, n_traj: int, n_spin: int, point: int = 0):
     return zx[:, :n_spin], zy[:, :n_spin]
 
 
-def collective_noise(seed: int, step: int, n_traj: int, point: int = 0):
+def collective_noise(seed: int, step: int, n_traj: int, point: int = 0, traj=None):
     """Standard normals g^x, g^y of shape (n_traj,) for one step."""
     k0, k1 = seed_key(seed)
-    k = np.arange(n_traj, dtype=np.uint64)
+    k = _traj_index(n_traj, traj)
     x0, x1, _, _ = philox4x32_10(np.uint64(0), k, np.uint64(step), _tagword(TAG_COLLECTIVE, point), k0, k1)
     return box_muller(x0, x1)
 
 
-def initial_signs(seed: int, n_traj: int, n_spin: int, point: int = 0):
+def initial_signs(seed: int, n_traj: int, n_spin: int, point: int = 0, traj=None):
     """+-1 signs (sx, sy), each (n_traj, n_spin), for the discrete initial sampling."""
     k0, k1 = seed_key(seed)
     n_slot = (n_spin + 63) // 64
     m = np.arange(n_slot, dtype=np.uint64)[None, :]
-    k = np.arange(n_traj, dtype=np.uint64)[:, None]
+    k = _traj_index(n_traj, traj)[:, None]
     words = philox4x32_10(m, k, np.uint64(0), _tagword(TAG_INIT, point), k0, k1)
     bits = np.zeros((n_traj, n_slot, 128), dtype=np.int8)
     for w in range(4):

@@ -59,6 +59,9 @@ class RunConfig:
     noise: bool = True
     response_eps: Optional[float] = None   # None: tangent-linear response copies
     init_state: Optional[tuple] = None     # (x, y, z) arrays (n_traj, n_spin)
+    traj: Optional[np.ndarray] = None      # trajectory indices (n_traj,) of the noise counters;
+                                           # None: 0 .. n_traj-1 (trajectories are independent,
+                                           # so any subset of an ensemble can be integrated alone)
 
     def resolved_burnin(self) -> int:
         return self.n_steps // 2 if self.burnin is None else int(self.burnin)
@@ -84,9 +87,9 @@ class RunResult:
     extra: dict = field(default_factory=dict)
 
 
-def initial_state(seed: int, n_traj: int, n_spin: int, s0z: float = 1.0, point: int = 0):
+def initial_state(seed: int, n_traj: int, n_spin: int, s0z: float = 1.0, point: int = 0, traj=None):
     """Discrete sampling of SM Sec. S1 step 3."""
-    sx, sy = philox.initial_signs(seed, n_traj, n_spin, point)
+    sx, sy = philox.initial_signs(seed, n_traj, n_spin, point, traj)
     sz = np.full((n_traj, n_spin), float(s0z))
     return sx, sy, sz
 
@@ -130,8 +133,8 @@ def noise_increments(cfg: RunConfig, pump: Pump, step: int):
         z1 = np.zeros(B)
         zN = np.zeros((B, n))
         return (z1, z1), (zN, zN)
-    gx, gy = philox.collective_noise(cfg.seed, step, B, cfg.point)
-    zx, zy = philox.pump_noise(cfg.seed, step, B, n, cfg.point)
+    gx, gy = philox.collective_noise(cfg.seed, step, B, cfg.point, cfg.traj)
+    zx, zy = philox.pump_noise(cfg.seed, step, B, n, cfg.point, cfg.traj)
     sg = np.sqrt(cfg.gamma * cfg.dt)
     sq = np.sqrt(cfg.dt)
     dxi = (sg * gx, sg * gy)
@@ -186,7 +189,7 @@ def run(cfg: RunConfig, pump: Optional[Pump] = None) -> RunResult:
     if cfg.init_state is not None:
         state = tuple(np.array(a, dtype=np.float64) for a in cfg.init_state)
     else:
-        state = initial_state(cfg.seed, B, cfg.n_spin, cfg.s0z, cfg.point)
+        state = initial_state(cfg.seed, B, cfg.n_spin, cfg.s0z, cfg.point, cfg.traj)
     norm0 = state[0] ** 2 + state[1] ** 2 + state[2] ** 2
 
     acc = np.zeros((B, 5))

@@ -180,3 +180,16 @@ def test_determinism():
     a, b = twa.run(cfg), twa.run(cfg)
     assert np.array_equal(a.traj_moments, b.traj_moments)
     assert np.array_equal(a.corr_blocks, b.corr_blocks)
+
+
+def test_trajectory_subset_equals_rows_of_full_ensemble():
+    """Trajectories are independent (their noise counters carry the trajectory
+    index), so integrating a subset reproduces those rows of the full run."""
+    n, B, T = 7, 9, 25
+    full = twa.run(twa.RunConfig(n_spin=n, w=1.7, alpha=0.8, n_traj=B, dt=2e-3, n_steps=T, seed=3, s0z=-1.0))
+    idx = np.array([8, 0, 5])
+    sub = twa.run(twa.RunConfig(n_spin=n, w=1.7, alpha=0.8, n_traj=3, dt=2e-3, n_steps=T, seed=3, s0z=-1.0,
+                                traj=idx))
+    for c in range(3):
+        assert np.array_equal(sub.final_state[c], full.final_state[c][idx])
+    assert np.array_equal(sub.traj_moments, full.traj_moments[idx])
