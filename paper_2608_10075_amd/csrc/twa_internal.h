@@ -62,7 +62,8 @@ struct EnsembleBuffers {
     void* Xop = nullptr;        // GT [C2][2P] rows: (s^a | zeta^a) of one column
     void* Dop = nullptr;        // GT [C2][P]  predictor increments
     void* s[2] = {nullptr, nullptr};   // ST [3][Bp][P] ping-pong state
-    void* dlt = nullptr;        // ST [3][Bp][P] predictor increment
+    void* dlt = nullptr;        // ST [3][Bp][P] predictor increment (kept only where response copies need it)
+    void* Sn = nullptr;         // ST [2][Bp] collective sums S^x, S^y of the step's input state
     void* Y = nullptr;          // ST [2][Bp][P] contraction output of stage 1 (and 2)
     void* part[2] = {nullptr, nullptr};// ST [3][nmt][Bp] partial spin sums: [0] current state, [1] predictor
     void* g = nullptr;          // ST [2][Bp] collective normals of the step
@@ -145,7 +146,7 @@ int launch_init_state(const Geometry& g, const EnsembleBuffers& b, const StepCon
 int launch_reduce_state(const Geometry& g, const void* s, void* part, hipStream_t st);
 int launch_noise(const Geometry& g, const EnsembleBuffers& b, const StepConsts& c, hipStream_t st);
 int launch_gemm(const Geometry& g, const EnsembleBuffers& b, const StepConsts& c, int stage,
-                bool tangent, int cur, bool store_y2, hipStream_t st);
+                bool tangent, int cur, bool store_y2, bool keep_dlt, hipStream_t st);
 int launch_seed_tangents(const Geometry& g, const EnsembleBuffers& b, int cur, hipStream_t st);
 int launch_observe(const Geometry& g, const EnsembleBuffers& b, const StepConsts& c, int cur,
                    bool tangents, hipStream_t st);

@@ -180,7 +180,7 @@ double linewidth_of(const std::vector<std::complex<double>>& corr, double tau) {
 void free_buffers(EnsembleBuffers& b) {
     void* ptrs[] = {b.A,      b.Xop,    b.Dop,  b.s[0], b.s[1],    b.dlt,     b.Y,      b.part[0],
                     b.part[1], b.g,     b.norm0, b.mom, b.tXop,    b.tDop,    b.ts[0],  b.ts[1],
-                    b.tdlt,   b.tY,     b.tpart[0], b.tpart[1], b.sm0, b.lag, b.step, b.diag};
+                    b.tdlt,   b.tY,     b.tpart[0], b.tpart[1], b.sm0, b.lag, b.step, b.diag, b.Sn};
     for (void* q : ptrs) hipFree(q);
     b = EnsembleBuffers();
 }
@@ -211,6 +211,7 @@ int alloc_buffers(const Geometry& g, bool tangents, int64_t L, int J, EnsembleBu
     TWA_A(b.s[0], 3 * Bp * P * se)
     TWA_A(b.s[1], 3 * Bp * P * se)
     TWA_A(b.dlt, 3 * Bp * P * se)
+    TWA_A(b.Sn, 2 * Bp * se)
     TWA_A(b.Y, 2 * Bp * P * se)
     TWA_A(b.part[0], 3 * nmt * Bp * se)
     TWA_A(b.part[1], 3 * nmt * Bp * se)

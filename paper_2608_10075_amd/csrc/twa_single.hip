@@ -15,13 +15,15 @@ int launch_step_kernels(const Geometry& g, EnsembleBuffers& b, const StepConsts&
     int rc;
     if ((rc = launch_noise(g, b, c, st))) return rc;
     if (tm) tm->s1.begin(st);
-    if ((rc = launch_gemm(g, b, c, 1, false, cur, false, st))) return rc;
+    // the primal predictor increment is stored only when the response copies
+    // of the step read it; otherwise the corrector recomputes it
+    if ((rc = launch_gemm(g, b, c, 1, false, cur, false, tan_active, st))) return rc;
     if (tm) tm->s1.end(st);
-    if (tan_active && (rc = launch_gemm(g, b, c, 1, true, cur, false, st))) return rc;
+    if (tan_active && (rc = launch_gemm(g, b, c, 1, true, cur, false, true, st))) return rc;
     if (tm) tm->s2.begin(st);
-    if ((rc = launch_gemm(g, b, c, 2, false, cur, tan_active, st))) return rc;
+    if ((rc = launch_gemm(g, b, c, 2, false, cur, tan_active, tan_active, st))) return rc;
     if (tm) tm->s2.end(st);
-    if (tan_active && (rc = launch_gemm(g, b, c, 2, true, cur, false, st))) return rc;
+    if (tan_active && (rc = launch_gemm(g, b, c, 2, true, cur, false, true, st))) return rc;
     return TWA_OK;
 }
 

@@ -52,6 +52,8 @@ struct GemmArgs {
     S* part_out;        // partial sums written
     const S* g;
     int store_y2;
+    S* Sn;              // [2][Bp] collective sums of the input state: stage 1 writes, stage 2 reads
+                        // (stage 2 recomputes the predictor increment when dlt is null)
     // tangent buffers (copy 0; copy offsets below)
     const S* t_cur;
     S* t_next;
@@ -279,6 +281,20 @@ __device__ __forceinline__ void stage_tile(const GemmArgs<PREC>& a, const int mt
             const S sx = v[0], sy = v[1];
             sS[t][0] = sx;
             sS[t][1] = sy;
+            if constexpr (KIND == KIND_PRIMAL) {
+                if (a.Sn) {
+                    if constexpr (STAGE == 1) {
+                        if (mt == 0) {
+                            a.Sn[k] = sx;
+                            a.Sn[Bp + k] = sy;
+                        }
+                    } else if (a.dlt == nullptr) {
+                        // sums of the step's input state, for the predictor increment
+                        sT[t][0] = a.Sn[k];
+                        sT[t][1] = a.Sn[Bp + k];
+                    }
+                }
+            }
             sG[t][0] = a.g[k];
             sG[t][1] = a.g[Bp + k];
             if constexpr (TCOPY) {
@@ -372,20 +388,36 @@ __device__ __forceinline__ void stage_tile(const GemmArgs<PREC>& a, const int mt
                     ps1 += y[r] + dy[r];
                     ps2 += z[r] + dz[r];
                 }
-                st4(a.dlt + off, dx);
-                st4(a.dlt + SP + off, dy);
-                st4(a.dlt + 2 * SP + off, dz);
+                if (a.dlt) {
+                    st4(a.dlt + off, dx);
+                    st4(a.dlt + SP + off, dy);
+                    st4(a.dlt + 2 * SP + off, dz);
+                }
                 st4(a.Y + off, yx);
                 st4(a.Y + SP + off, yy);
                 stg4<PREC>(a.Dop + opcol(k, 0) * P + i0, dx);
                 stg4<PREC>(a.Dop + opcol(k, 1) * P + i0, dy);
             } else if constexpr (KIND == KIND_PRIMAL && STAGE == 2) {
                 S dx[4], dy[4], dz[4], yx[4], yy[4], nx[4], ny[4], nz[4];
-                ld4(a.dlt + off, dx);
-                ld4(a.dlt + SP + off, dy);
-                ld4(a.dlt + 2 * SP + off, dz);
                 ld4(a.Y + off, yx);
                 ld4(a.Y + SP + off, yy);
+                if (a.dlt) {
+                    ld4(a.dlt + off, dx);
+                    ld4(a.dlt + SP + off, dy);
+                    ld4(a.dlt + 2 * SP + off, dz);
+                } else {
+                    // the predictor increment, recomputed exactly as the predictor
+                    // stage formed it (same operands, same operation order)
+                    const S hxn = c1 * sT[kl][0] + c2 * sG[kl][0];
+                    const S hyn = c1 * sT[kl][1] + c2 * sG[kl][1];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const S Hx = yx[r] + hxn, Hy = yy[r] + hyn;
+                        dx[r] = z[r] * Hx;
+                        dy[r] = z[r] * Hy;
+                        dz[r] = -(x[r] * Hx + y[r] * Hy);
+                    }
+                }
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const S ax = yx[r] + acc[bi][2 * p][r], ay = yy[r] + acc[bi][2 * p + 1][r];
@@ -765,7 +797,7 @@ static int dispatch_cfg(const GemmArgs<PREC>& a, int cfg, int stage, int kind, i
 // arguments of a forward-run contraction launch (primal or response copies)
 template <int PREC>
 static GemmArgs<PREC> make_args(const Geometry& g, const EnsembleBuffers& b, const StepConsts& c, int stage,
-                                bool tangent, int cur, bool store_y2) {
+                                bool tangent, int cur, bool store_y2, bool keep_dlt) {
     typedef typename Prec<PREC>::G G;
     typedef typename Prec<PREC>::S S;
     GemmArgs<PREC> a{};
@@ -781,7 +813,8 @@ static GemmArgs<PREC> make_args(const Geometry& g, const EnsembleBuffers& b, con
     a.c2 = (S)c.c2;
     a.s_cur = static_cast<const S*>(b.s[cur]);
     a.s_next = static_cast<S*>(b.s[1 - cur]);
-    a.dlt = static_cast<S*>(b.dlt);
+    a.dlt = (tangent || keep_dlt) ? static_cast<S*>(b.dlt) : nullptr;
+    a.Sn = static_cast<S*>(b.Sn);
     a.Y = static_cast<S*>(b.Y);
     a.Dop = static_cast<G*>(b.Dop);
     a.g = static_cast<const S*>(b.g);
@@ -835,19 +868,19 @@ static GemmArgs<PREC> make_args(const Geometry& g, const EnsembleBuffers& b, con
 
 template <int PREC>
 static int launch_gemm_p(const Geometry& g, const EnsembleBuffers& b, const StepConsts& c, int stage,
-                         bool tangent, int cur, bool store_y2, hipStream_t st) {
-    const GemmArgs<PREC> a = make_args<PREC>(g, b, c, stage, tangent, cur, store_y2);
+                         bool tangent, int cur, bool store_y2, bool keep_dlt, hipStream_t st) {
+    const GemmArgs<PREC> a = make_args<PREC>(g, b, c, stage, tangent, cur, store_y2, keep_dlt);
     return dispatch_cfg<PREC>(a, g.cfg, stage, tangent ? KIND_TANGENT : KIND_PRIMAL, g.P, g.C2, tangent ? 2 : 1,
                               st);
 }
 
 int launch_gemm(const Geometry& g, const EnsembleBuffers& b, const StepConsts& c, int stage, bool tangent,
-                int cur, bool store_y2, hipStream_t st) {
+                int cur, bool store_y2, bool keep_dlt, hipStream_t st) {
     switch (g.precision) {
-        case TWA_PREC_FP64: return launch_gemm_p<TWA_PREC_FP64>(g, b, c, stage, tangent, cur, store_y2, st);
-        case TWA_PREC_FP32: return launch_gemm_p<TWA_PREC_FP32>(g, b, c, stage, tangent, cur, store_y2, st);
-        case TWA_PREC_BF16: return launch_gemm_p<TWA_PREC_BF16>(g, b, c, stage, tangent, cur, store_y2, st);
-        case TWA_PREC_FP16: return launch_gemm_p<TWA_PREC_FP16>(g, b, c, stage, tangent, cur, store_y2, st);
+        case TWA_PREC_FP64: return launch_gemm_p<TWA_PREC_FP64>(g, b, c, stage, tangent, cur, store_y2, keep_dlt, st);
+        case TWA_PREC_FP32: return launch_gemm_p<TWA_PREC_FP32>(g, b, c, stage, tangent, cur, store_y2, keep_dlt, st);
+        case TWA_PREC_BF16: return launch_gemm_p<TWA_PREC_BF16>(g, b, c, stage, tangent, cur, store_y2, keep_dlt, st);
+        case TWA_PREC_FP16: return launch_gemm_p<TWA_PREC_FP16>(g, b, c, stage, tangent, cur, store_y2, keep_dlt, st);
     }
     set_error("unknown precision");
     return TWA_EINVAL;
@@ -963,7 +996,8 @@ static int grouped_prepare_p(const std::vector<Geometry>& gs, const std::vector<
         for (int cur = 0; cur < 2; ++cur) {
             std::vector<GemmArgs<PREC>> h((size_t)np);
             for (int p = 0; p < np; ++p) {
-                h[(size_t)p] = make_args<PREC>(gs[(size_t)p], bs[(size_t)p], cs[(size_t)p], stage, false, cur, false);
+                h[(size_t)p] = make_args<PREC>(gs[(size_t)p], bs[(size_t)p], cs[(size_t)p], stage, false, cur, false,
+                                               false);
                 h[(size_t)p].nnt = (int)(gs[(size_t)p].C2 / tc.nt);
             }
             TWA_HIP_CHECK(hipMalloc(&pl.d_args[stage - 1][cur], h.size() * sizeof(GemmArgs<PREC>)));
