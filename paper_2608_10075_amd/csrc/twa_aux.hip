@@ -2,6 +2,8 @@
 // initial sampling (SM Sec. S1 step 3), per-step noise draws (Eq. (S1)),
 // time-averaged moments (SM Sec. S1 steps 5-6 and the closing remark on time
 // averaging) and the two-time accumulation (Eq. (S3) and the response copies).
+#include <algorithm>
+
 #include "twa_internal.h"
 #include "twa_device.h"
 
@@ -139,37 +141,41 @@ __global__ void noise_kernel(int64_t N, int64_t B, int64_t P, int64_t Bp, uint32
                              uint32_t point, const int64_t* step, typename Prec<PREC>::G* Xop,
                              typename Prec<PREC>::S* g) {
     typedef typename Prec<PREC>::S S;
+    // grid: x over Philox slots (pairs of spins), y over trajectories (strided)
     const int64_t nslot = (N + 1) / 2;
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= B * nslot) return;
-    const int64_t k = t / nslot, m = t % nslot;
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= nslot) return;
     const uint32_t n = (uint32_t)step[0];
-    const U4 w = philox4x32_10(U4{(uint32_t)m, (uint32_t)k, n, TAG_PUMP | (point << 8)}, k0, k1);
-    S z0, z1, z2, z3;
-    box_muller(w.x, w.y, z0, z1);
-    box_muller(w.z, w.w, z2, z3);
-    const int64_t i = 2 * m;
-    typename Prec<PREC>::G* cx = Xop + opcol(k, 0) * 2 * P + P;
-    typename Prec<PREC>::G* cy = Xop + opcol(k, 1) * 2 * P + P;
-    cx[i] = Prec<PREC>::to_g(z0);
-    cy[i] = Prec<PREC>::to_g(z1);
-    if (i + 1 < N) {
-        cx[i + 1] = Prec<PREC>::to_g(z2);
-        cy[i + 1] = Prec<PREC>::to_g(z3);
-    }
-    if (m == 0) {
-        const U4 v = philox4x32_10(U4{0u, (uint32_t)k, n, TAG_COLLECTIVE | (point << 8)}, k0, k1);
-        S g0, g1;
-        box_muller(v.x, v.y, g0, g1);
-        g[k] = g0;
-        g[Bp + k] = g1;
+    for (int64_t k = blockIdx.y; k < B; k += gridDim.y) {
+        const U4 w = philox4x32_10(U4{(uint32_t)m, (uint32_t)k, n, TAG_PUMP | (point << 8)}, k0, k1);
+        S z0, z1, z2, z3;
+        box_muller(w.x, w.y, z0, z1);
+        box_muller(w.z, w.w, z2, z3);
+        const int64_t i = 2 * m;
+        typename Prec<PREC>::G* cx = Xop + opcol(k, 0) * 2 * P + P;
+        typename Prec<PREC>::G* cy = Xop + opcol(k, 1) * 2 * P + P;
+        cx[i] = Prec<PREC>::to_g(z0);
+        cy[i] = Prec<PREC>::to_g(z1);
+        if (i + 1 < N) {
+            cx[i + 1] = Prec<PREC>::to_g(z2);
+            cy[i + 1] = Prec<PREC>::to_g(z3);
+        }
+        if (m == 0) {
+            const U4 v = philox4x32_10(U4{0u, (uint32_t)k, n, TAG_COLLECTIVE | (point << 8)}, k0, k1);
+            S g0, g1;
+            box_muller(v.x, v.y, g0, g1);
+            g[k] = g0;
+            g[Bp + k] = g1;
+        }
     }
 }
 
 template <int PREC>
 static int noise_t(const Geometry& g, const EnsembleBuffers& b, const StepConsts& c, hipStream_t st) {
-    const int64_t n = g.B * ((g.N + 1) / 2);
-    hipLaunchKernelGGL(noise_kernel<PREC>, dim3(nblocks(n, 256)), dim3(256), 0, st, g.N, g.B, g.P, g.Bp, c.key0,
+    const int64_t nslot = (g.N + 1) / 2;
+    hipLaunchKernelGGL(noise_kernel<PREC>, dim3(nblocks(nslot, 256), (unsigned)std::min<int64_t>(g.B, 65535)),
+                       dim3(256), 0, st, g.N, g.B, g.P,
+                       g.Bp, c.key0,
                        c.key1, (uint32_t)c.point, (const int64_t*)b.step,
                        static_cast<typename Prec<PREC>::G*>(b.Xop), static_cast<typename Prec<PREC>::S*>(b.g));
     TWA_HIP_CHECK(hipGetLastError());
