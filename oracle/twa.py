@@ -20,8 +20,12 @@ notes of the repository):
 
 * Calculus / integrator: the paper integrates with a semi-implicit scheme and
   states that the equations preserve the spin length, which holds in the
-  Stratonovich sense.  Integrator used here: stochastic Heun (Euler predictor,
-  trapezoidal corrector, the same noise increments in both stages).
+  Stratonovich sense.  Integrators here: stochastic Heun (Euler predictor,
+  trapezoidal corrector, the same noise increments in both stages; the
+  default) and the semi-implicit midpoint scheme the paper cites (Mentink et
+  al., 2010): each stage is the implicit midpoint rule with the field frozen,
+  first at s_n, then at the midpoint of s_n and the first stage's result,
+  which rotates every spin and keeps its length exactly.
 * Discretisation of the noises over one step dt: xi^a dt -> sqrt(Gamma dt) g^a,
   chi^a dt -> sqrt(dt) (F zeta^a) with F the PSD square root of w_ij and g,
   zeta independent standard normals.
@@ -59,6 +63,7 @@ class RunConfig:
     noise: bool = True
     response_eps: Optional[float] = None   # None: tangent-linear response copies
     init_state: Optional[tuple] = None     # (x, y, z) arrays (n_traj, n_spin)
+    integrator: str = "heun"               # "heun" or "sib" (semi-implicit midpoint)
     traj: Optional[np.ndarray] = None      # trajectory indices (n_traj,) of the noise counters;
                                            # None: 0 .. n_traj-1 (trajectories are independent,
                                            # so any subset of an ensemble can be integrated alone)
@@ -151,6 +156,51 @@ def heun_step(state, W, gamma, dt, dxi, dchi):
     return new, (d1, pred, d2)
 
 
+def fields(state, W, gamma, dt, dxi, dchi):
+    """h^x_i dt and h^y_i dt of Eq. (S1) at a given state (as in ``increment``)."""
+    return increment(state, W, gamma, dt, dxi, dchi)[3]
+
+
+def midpoint_rotation(state, hx, hy):
+    """Solve s' = s + ((s + s') / 2) x b spin by spin, with b = (h^y dt, -h^x dt, 0)
+    (so that s x b is the increment of Eq. (S1)): the implicit midpoint rule of
+    ds = s x b with b held fixed, a 3 x 3 linear system per spin.  Writing
+    [b] for the matrix of b x ., it reads (I + [b]/2) s' = (I - [b]/2) s."""
+    x, y, z = state
+    bx, by = hy, -hx
+    B, n = x.shape
+    K = np.zeros((B, n, 3, 3))
+    K[..., 0, 2] = by           # [b] = [[0, -bz, by], [bz, 0, -bx], [-by, bx, 0]], bz = 0
+    K[..., 1, 2] = -bx
+    K[..., 2, 0] = -by
+    K[..., 2, 1] = bx
+    eye = np.eye(3)
+    s = np.stack([x, y, z], axis=-1)[..., None]
+    rhs = (eye - 0.5 * K) @ s
+    out = np.linalg.solve(eye + 0.5 * K, rhs)[..., 0]
+    return out[..., 0], out[..., 1], out[..., 2]
+
+
+def sib_step(state, W, gamma, dt, dxi, dchi):
+    """Semi-implicit midpoint step (Mentink et al.): s~ = the midpoint rule with
+    the field at s_n; s_{n+1} = the midpoint rule with the field at (s_n + s~)/2;
+    the same noise increments in both stages."""
+    hx, hy = fields(state, W, gamma, dt, dxi, dchi)
+    pred = midpoint_rotation(state, hx, hy)
+    mid = tuple(0.5 * (a + b) for a, b in zip(state, pred))
+    hx2, hy2 = fields(mid, W, gamma, dt, dxi, dchi)
+    return midpoint_rotation(state, hx2, hy2), pred
+
+
+def step(cfg: RunConfig, state, W, dxi, dchi):
+    """One step of the configured integrator."""
+    if cfg.integrator == "heun":
+        return heun_step(state, W, cfg.gamma, cfg.dt, dxi, dchi)[0]
+    if cfg.integrator == "sib":
+        return sib_step(state, W, cfg.gamma, cfg.dt, dxi, dchi)[0]
+    raise ValueError("unknown integrator %r" % cfg.integrator)
+
+
 def heun_step_tangent(state, dstate, W, gamma, dt, dxi, dchi, parts=None):
     """Tangent-linear Heun step (same noise) along ``dstate``."""
     if parts is None:
@@ -231,12 +281,17 @@ def run(cfg: RunConfig, pump: Optional[Pump] = None) -> RunResult:
             tan_x = (st[0] + eps, st[1].copy(), st[2].copy())
             tan_y = (st[0].copy(), st[1] + eps, st[2].copy())
 
+    if L > 0 and cfg.integrator != "heun":
+        raise NotImplementedError("two-time response copies are defined for the Heun integrator")
     if L > 0 and burn == 0:
         start_lags(state)
         lag_accumulate(0, state)
     for n in range(T):
         dxi, dchi = noise_increments(cfg, pump, n)
-        new, parts = heun_step(state, W, cfg.gamma, cfg.dt, dxi, dchi)
+        if cfg.integrator == "heun":
+            new, parts = heun_step(state, W, cfg.gamma, cfg.dt, dxi, dchi)
+        else:
+            new = step(cfg, state, W, dxi, dchi)
         if tan_x is not None:
             if eps is None:
                 tan_x = heun_step_tangent(state, tan_x, W, cfg.gamma, cfg.dt, dxi, dchi, parts)
@@ -263,9 +318,10 @@ def run(cfg: RunConfig, pump: Optional[Pump] = None) -> RunResult:
 
 
 def run_steps(state, pump: Pump, cfg: RunConfig, first_step: int, n_steps: int):
-    """Advance a given state by ``n_steps`` Heun steps starting at step index
-    ``first_step`` (noise counters follow the absolute step index)."""
+    """Advance a given state by ``n_steps`` steps of the configured integrator
+    starting at step index ``first_step`` (noise counters follow the absolute
+    step index)."""
     for n in range(first_step, first_step + n_steps):
         dxi, dchi = noise_increments(cfg, pump, n)
-        state, _ = heun_step(state, pump.W, cfg.gamma, cfg.dt, dxi, dchi)
+        state = step(cfg, state, pump.W, dxi, dchi)
     return state
