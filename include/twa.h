@@ -60,6 +60,11 @@ extern "C" {
 
 /* ---- integrators ------------------------------------------------------ */
 #define TWA_INT_HEUN    0   /* stochastic Heun, Stratonovich reading of Eq. (S1) */
+#define TWA_INT_SIB     1   /* semi-implicit midpoint scheme (the spin-length-preserving
+                               integrator the paper cites): each of the two stages is the
+                               implicit midpoint rule with the field frozen, first at s_n,
+                               then at the midpoint of s_n and the first stage's result;
+                               not available with n_lags > 0 or in twa_adjoint */
 
 /* ======================================================================
  * Pump: Eq. (2) and its channel decomposition.
@@ -118,7 +123,7 @@ typedef struct twa_params {
     double gamma;            /* collective decay rate Gamma (> 0)                  */
     double s0z;              /* initial s^z of every spin: +1 excited, -1 ground   */
     int64_t burnin;          /* steps before the averaging window; < 0 = n_steps/2 */
-    int32_t integrator;      /* TWA_INT_HEUN                                       */
+    int32_t integrator;      /* TWA_INT_HEUN or TWA_INT_SIB                        */
     int32_t precision;       /* TWA_PREC_*                                         */
     int64_t n_lags;          /* two-time lags L (0 = no two-time correlation)      */
     int64_t lag_stride;      /* steps per lag; <= 0 = max(1, (n_steps-burnin)/L)   */
@@ -229,9 +234,10 @@ typedef struct twa_batch_opts {
     double s0z;
     int32_t precision;       /* TWA_PREC_FP32 / BF16 / FP16                      */
     int32_t use_graph;       /* capture the step loop in a hipGraph (default 1)  */
-    int32_t steps_per_graph; /* steps captured per graph replay (<= 0: 64)       */
+    int32_t steps_per_graph; /* steps captured per graph replay (<= 0: 16)       */
     const char* tune_cache;  /* autotuner cache file (NULL: no cache)            */
     void* stream;            /* hipStream_t                                      */
+    int32_t integrator;      /* TWA_INT_HEUN (default) or TWA_INT_SIB            */
 } twa_batch_opts;
 
 TWA_API void twa_batch_opts_default(twa_batch_opts* o);

@@ -24,6 +24,7 @@ LIB_PATH = os.path.join(_HERE, "libtwa.so")
 
 TWA_OK, TWA_EINVAL, TWA_ENOMEM, TWA_EHIP, TWA_ENOTPSD, TWA_EUNSTABLE = 0, -1, -2, -3, -4, -5
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "fp16": 3}
+INTEGRATORS = {"heun": 0, "sib": 1}
 
 
 class TWAError(RuntimeError):
@@ -68,7 +69,8 @@ class _Point(C.Structure):
 class _BatchOpts(C.Structure):
     _fields_ = [("n_traj", C.c_int64), ("n_steps", C.c_int64), ("burnin", C.c_int64), ("gamma", C.c_double),
                 ("s0z", C.c_double), ("precision", C.c_int32), ("use_graph", C.c_int32),
-                ("steps_per_graph", C.c_int32), ("tune_cache", C.c_char_p), ("stream", C.c_void_p)]
+                ("steps_per_graph", C.c_int32), ("tune_cache", C.c_char_p), ("stream", C.c_void_p),
+                ("integrator", C.c_int32)]
 
 
 def load_library(path: str = LIB_PATH) -> C.CDLL:
@@ -189,11 +191,14 @@ def run(pump: Pump, n_traj: int, dt: float, n_steps: int, seed: int = 0, *, gamm
         s0z: float = 1.0, burnin: int = -1, precision: str = "fp32", n_lags: int = 0, lag_stride: int = 0,
         point: int = 0, tile_config: int = -1, init_state: Optional[np.ndarray] = None, timing: bool = False,
         use_graph: bool = True, kappa: float = 0.25, stream=None, want_traj: bool = False,
-        want_final_state: bool = False, want_lags: bool = False, allow_unstable: bool = False) -> RunResult:
-    """twa_run: n_traj trajectories of Eq. (S1), n_steps Heun steps of size dt."""
+        want_final_state: bool = False, want_lags: bool = False, allow_unstable: bool = False,
+        integrator: str = "heun") -> RunResult:
+    """twa_run: n_traj trajectories of Eq. (S1), n_steps steps of size dt of the
+    stochastic Heun ("heun") or semi-implicit midpoint ("sib") integrator."""
     p = _Params()
     _lib.twa_params_default(C.byref(p))
     p.pump = pump.handle
+    p.integrator = INTEGRATORS[integrator]
     p.gamma, p.s0z, p.burnin = gamma, s0z, burnin
     p.precision = PRECISIONS[precision]
     p.n_lags, p.lag_stride, p.point, p.tile_config = n_lags, lag_stride, point, tile_config
@@ -235,7 +240,7 @@ def run(pump: Pump, n_traj: int, dt: float, n_steps: int, seed: int = 0, *, gamm
 
 def run_batch(points, n_traj: int, n_steps: int, *, burnin: int = -1, gamma: float = 1.0, s0z: float = 1.0,
               precision: str = "fp32", use_graph: bool = True, steps_per_graph: int = 16,
-              tune_cache: Optional[str] = None, stream=None):
+              tune_cache: Optional[str] = None, stream=None, integrator: str = "heun"):
     """twa_run_batch: points is a sequence of (N, w, alpha, dt, seed); returns
     one observables dict per point (Philox point index = position)."""
     pts = (_Point * len(points))()
@@ -249,6 +254,7 @@ def run_batch(points, n_traj: int, n_steps: int, *, burnin: int = -1, gamma: flo
     o.steps_per_graph = steps_per_graph
     o.tune_cache = tune_cache.encode() if tune_cache else None
     o.stream = _stream_ptr(stream)
+    o.integrator = INTEGRATORS[integrator]
     outs = (_Obs * len(points))()
     _check(_lib.twa_run_batch(pts, len(points), C.byref(o), outs))
     return [_obs_dict(x) for x in outs]

@@ -573,6 +573,10 @@ extern "C" TWA_API int twa_adjoint(const twa_params* p, int64_t n_traj, double d
         set_error("twa_adjoint: needs a pump from twa_build_pump with w > 0");
         return TWA_EINVAL;
     }
+    if (p->integrator != TWA_INT_HEUN) {
+        set_error("twa_adjoint: the reverse sweep is defined for the Heun integrator");
+        return TWA_EINVAL;
+    }
     const int64_t burnin = p->burnin < 0 ? n_steps / 2 : p->burnin;
     if (burnin >= n_steps) {
         set_error("twa_adjoint: the averaging window is empty");

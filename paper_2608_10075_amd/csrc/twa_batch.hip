@@ -152,6 +152,7 @@ int build_batch(const twa_point* pts, int np, const twa_batch_opts* o, const std
     for (int p = 0; p < np; ++p) {
         Geometry& g = bt.gs[(size_t)p];
         g = make_geometry(o->precision, cfg, pts[p].N, o->n_traj);
+        g.integrator = o->integrator;
         EnsembleBuffers& b = bt.bs[(size_t)p];
         if ((rc = alloc_buffers(g, false, 0, (int)std::min<int64_t>(32, o->n_traj), b))) return rc;
         hipFree(b.step);
@@ -258,7 +259,7 @@ int run_steps(Batch& bt, int64_t n0, int64_t n1, int64_t burnin, int& cur, bool 
 
 std::string tune_key(const twa_point* pts, int np, const twa_batch_opts* o) {
     std::ostringstream s;
-    s << "prec" << o->precision << ":B" << o->n_traj << ":N";
+    s << "prec" << o->precision << ":int" << o->integrator << ":B" << o->n_traj << ":N";
     for (int p = 0; p < np; ++p) s << (p ? "," : "") << pts[p].N;
     return s.str();
 }
@@ -284,10 +285,11 @@ void store_cfg(const char* path, const std::string& key, int cfg) {
 // measures a few grouped steps for each candidate tile configuration
 static int autotune(const twa_point* pts, int np, const twa_batch_opts* o, const std::vector<twa_pump*>& pumps,
                     hipStream_t st, int* best_cfg, double* best_ms) {
-    const int cands[] = {2, 3, 1};
+    const int cands[] = {2, 3, 1, 7};
     *best_cfg = -1;
     *best_ms = 1e300;
     for (int cfg : cands) {
+        if (cfg == 7 && o->precision == TWA_PREC_FP64) continue;
         Batch bt;
         int rc = build_batch(pts, np, o, pumps, cfg, bt, st);
         if (rc == TWA_OK) {
@@ -329,6 +331,10 @@ int run_batch(const twa_point* pts, int np, const twa_batch_opts* o, twa_observa
         set_error("twa_run_batch: need points, options, outputs, n_traj >= 1, n_steps >= 1, gamma > 0");
         return TWA_EINVAL;
     }
+    if (o->integrator != TWA_INT_HEUN && o->integrator != TWA_INT_SIB) {
+        set_error("twa_run_batch: integrator must be TWA_INT_HEUN or TWA_INT_SIB");
+        return TWA_EINVAL;
+    }
     if (o->precision != TWA_PREC_FP32 && o->precision != TWA_PREC_BF16 && o->precision != TWA_PREC_FP16) {
         set_error("twa_run_batch: precision must be FP32, BF16 or FP16");
         return TWA_EINVAL;
@@ -368,7 +374,7 @@ int run_batch(const twa_point* pts, int np, const twa_batch_opts* o, twa_observa
     for (int p = 0; p < np && rc == TWA_OK; ++p) rc = twa_build_pump(pts[p].N, pts[p].w, pts[p].alpha, &pumps[(size_t)p]);
     if (rc) goto cleanup;
     cfg = cached_cfg(o->tune_cache, key);
-    if (cfg < 0 || cfg > 3) {
+    if (cfg < 0 || (cfg > 3 && cfg != 7) || (cfg == 7 && o->precision == TWA_PREC_FP64)) {
         if ((rc = autotune(pts, np, o, pumps, st, &cfg, &tune_ms))) goto cleanup;
         store_cfg(o->tune_cache, key, cfg);
     }
@@ -457,6 +463,7 @@ TWA_API void twa_batch_opts_default(twa_batch_opts* o) {
     o->steps_per_graph = 16;
     o->tune_cache = nullptr;
     o->stream = nullptr;
+    o->integrator = TWA_INT_HEUN;
 }
 
 TWA_API int twa_run_batch(const twa_point* pts, int n_points, const twa_batch_opts* o, twa_observables* outs) {

@@ -50,6 +50,7 @@ int state_elt_bytes(int precision);
 struct Geometry {
     int precision;
     int cfg;
+    int integrator = TWA_INT_HEUN;
     int64_t N, B;        // atoms, trajectories
     int64_t P, Bp;       // padded
     int64_t nmt;         // P / MT
@@ -131,7 +132,7 @@ struct GroupedPlan {
     void* d_args[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};   // [stage-1][cur] per-ensemble arguments
     int4* d_tiles[2] = {nullptr, nullptr};
     int ntiles[2] = {0, 0};
-    int grid = 0, cfg = 0, precision = 0;
+    int grid = 0, cfg = 0, precision = 0, integrator = TWA_INT_HEUN;
     int64_t* step = nullptr;
 };
 int grouped_prepare(const std::vector<Geometry>& gs, const std::vector<EnsembleBuffers>& bs,

@@ -70,8 +70,14 @@ struct GraphCache {
 int run_single(const twa_params* p, int64_t n_traj, double dt, int64_t n_steps, uint64_t seed,
                twa_observables* out, const twa_outputs* outs) {
     if (!p || !p->pump || !out || n_traj < 1 || n_steps < 0 || !(dt > 0) || !std::isfinite(dt) ||
-        !(p->gamma > 0) || !std::isfinite(p->gamma) || p->integrator != TWA_INT_HEUN) {
-        set_error("twa_run: need params with a pump, n_traj >= 1, n_steps >= 0, dt > 0, gamma > 0, Heun");
+        !(p->gamma > 0) || !std::isfinite(p->gamma) ||
+        (p->integrator != TWA_INT_HEUN && p->integrator != TWA_INT_SIB)) {
+        set_error("twa_run: need params with a pump, n_traj >= 1, n_steps >= 0, dt > 0, gamma > 0, "
+                  "integrator TWA_INT_HEUN or TWA_INT_SIB");
+        return TWA_EINVAL;
+    }
+    if (p->integrator == TWA_INT_SIB && p->n_lags > 0) {
+        set_error("twa_run: the two-time response copies are defined for the Heun integrator (n_lags must be 0)");
         return TWA_EINVAL;
     }
     if (p->precision < TWA_PREC_FP64 || p->precision > TWA_PREC_FP16) {
@@ -99,7 +105,8 @@ int run_single(const twa_params* p, int64_t n_traj, double dt, int64_t n_steps, 
         set_error("twa_run: unknown tile configuration");
         return TWA_EINVAL;
     }
-    const Geometry g = make_geometry(p->precision, cfg, N, B);
+    Geometry g = make_geometry(p->precision, cfg, N, B);
+    g.integrator = p->integrator;
     const int J = (int)std::min<int64_t>(32, B);
     const bool tangents = L > 0;
 

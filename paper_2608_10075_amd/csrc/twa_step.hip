@@ -86,7 +86,25 @@ struct GemmArgs {
     int src_on;             // the state produced by this backward step is observed
 };
 
-enum { KIND_PRIMAL = 0, KIND_TANGENT = 1, KIND_STORE = 2, KIND_ADJ2 = 3, KIND_ADJ1 = 4 };
+enum { KIND_PRIMAL = 0, KIND_TANGENT = 1, KIND_STORE = 2, KIND_ADJ2 = 3, KIND_ADJ1 = 4, KIND_SIB = 5 };
+
+// Semi-implicit midpoint stage (the scheme the paper cites for its
+// spin-length-preserving integration): solve s' = s + ((s + s')/2) x b with
+// b = (H^y, -H^x, 0) frozen, i.e. (I + [beta]) s' = (I - [beta]) s with
+// beta = b/2 and [beta] the matrix of beta x .; the closed-form inverse of
+// I + [beta] is (I - [beta] + beta beta^T) / (1 + |beta|^2).  A rotation:
+// the spin length is kept exactly (up to rounding).
+template <typename S>
+__device__ __forceinline__ void midpoint_rotate(S x, S y, S z, S Hx, S Hy, S& ox, S& oy, S& oz) {
+    const S bx = S(0.5) * Hy, by = S(-0.5) * Hx;
+    // a = s - beta x s, beta x s = (by z, -bx z, bx y - by x)
+    const S ax = x - by * z, ay = y + bx * z, az = z - (bx * y - by * x);
+    const S bd = bx * ax + by * ay;
+    const S inv = S(1) / (S(1) + bx * bx + by * by);
+    ox = (ax - by * az + bx * bd) * inv;
+    oy = (ay + bx * az + by * bd) * inv;
+    oz = (az - (bx * ay - by * ax)) * inv;
+}
 
 template <typename S>
 __device__ __forceinline__ void ld4(const S* p, S (&v)[4]) {
@@ -281,14 +299,14 @@ __device__ __forceinline__ void stage_tile(const GemmArgs<PREC>& a, const int mt
             const S sx = v[0], sy = v[1];
             sS[t][0] = sx;
             sS[t][1] = sy;
-            if constexpr (KIND == KIND_PRIMAL) {
+            if constexpr (KIND == KIND_PRIMAL || KIND == KIND_SIB) {
                 if (a.Sn) {
                     if constexpr (STAGE == 1) {
                         if (mt == 0) {
                             a.Sn[k] = sx;
                             a.Sn[Bp + k] = sy;
                         }
-                    } else if (a.dlt == nullptr) {
+                    } else if (a.dlt == nullptr || KIND == KIND_SIB) {
                         // sums of the step's input state, for the predictor increment
                         sT[t][0] = a.Sn[k];
                         sT[t][1] = a.Sn[Bp + k];
@@ -397,6 +415,48 @@ __device__ __forceinline__ void stage_tile(const GemmArgs<PREC>& a, const int mt
                 st4(a.Y + SP + off, yy);
                 stg4<PREC>(a.Dop + opcol(k, 0) * P + i0, dx);
                 stg4<PREC>(a.Dop + opcol(k, 1) * P + i0, dy);
+            } else if constexpr (KIND == KIND_SIB && STAGE == 1) {
+                // predictor: the midpoint rule with the field at s_n
+                S dx[4], dy[4], yx[4], yy[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const S ax = acc[bi][2 * p][r], ay = acc[bi][2 * p + 1][r];
+                    S px, py, pz;
+                    midpoint_rotate(x[r], y[r], z[r], ax + hx0, ay + hy0, px, py, pz);
+                    dx[r] = px - x[r];
+                    dy[r] = py - y[r];
+                    yx[r] = ax;
+                    yy[r] = ay;
+                    ps0 += px;
+                    ps1 += py;
+                    ps2 += pz;
+                }
+                st4(a.Y + off, yx);
+                st4(a.Y + SP + off, yy);
+                stg4<PREC>(a.Dop + opcol(k, 0) * P + i0, dx);
+                stg4<PREC>(a.Dop + opcol(k, 1) * P + i0, dy);
+            } else if constexpr (KIND == KIND_SIB && STAGE == 2) {
+                // corrector: the midpoint rule from s_n with the field at the
+                // midpoint m = s_n + D/2: contraction Y1 + A_left D / 2, sums (S_n + S~)/2
+                S yx[4], yy[4], nx[4], ny[4], nz[4];
+                ld4(a.Y + off, yx);
+                ld4(a.Y + SP + off, yy);
+                const S hxm = c1 * (S(0.5) * (sT[kl][0] + Sx)) + c2 * sG[kl][0];
+                const S hym = c1 * (S(0.5) * (sT[kl][1] + Sy)) + c2 * sG[kl][1];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const S Hx = (yx[r] + S(0.5) * acc[bi][2 * p][r]) + hxm;
+                    const S Hy = (yy[r] + S(0.5) * acc[bi][2 * p + 1][r]) + hym;
+                    midpoint_rotate(x[r], y[r], z[r], Hx, Hy, nx[r], ny[r], nz[r]);
+                    ps0 += nx[r];
+                    ps1 += ny[r];
+                    ps2 += nz[r];
+                }
+                st4(a.s_next + off, nx);
+                st4(a.s_next + SP + off, ny);
+                st4(a.s_next + 2 * SP + off, nz);
+                stg4<PREC>(a.Xnext + opcol(k, 0) * a.ldxn + i0, nx);
+                stg4<PREC>(a.Xnext + opcol(k, 1) * a.ldxn + i0, ny);
             } else if constexpr (KIND == KIND_PRIMAL && STAGE == 2) {
                 S dx[4], dy[4], dz[4], yx[4], yy[4], nx[4], ny[4], nz[4];
                 ld4(a.Y + off, yx);
@@ -641,7 +701,7 @@ __device__ __forceinline__ void stage_tile(const GemmArgs<PREC>& a, const int mt
     }
     if constexpr (KIND != KIND_STORE) {
         __syncthreads();
-        if constexpr (KIND == KIND_PRIMAL || KIND == KIND_TANGENT || KIND == KIND_ADJ2) {
+        if constexpr (KIND == KIND_PRIMAL || KIND == KIND_SIB || KIND == KIND_TANGENT || KIND == KIND_ADJ2) {
             // ADJ2: channels 0, 1 are the spin sums of nu1 (its z channel is zero)
             S* po = a.part_out + (TCOPY ? cp * a.t_part_copy : 0);
             for (int t = tid; t < 3 * NTRJ; t += NTHR) {
@@ -682,7 +742,7 @@ __global__ __launch_bounds__(64 * WMW * WNW) void heun_stage_kernel(GemmArgs<PRE
     const int b = (int)blockIdx.x, x = b % 8, j = b / 8;
     const int L = x * q + (x < r ? x : r) + j;
     stage_tile<PREC, MT, NT, KB, WMW, WNW, NST, STAGE, KIND>(a, L / nnt, L % nnt, (int)blockIdx.z);
-    if constexpr (KIND == KIND_PRIMAL && STAGE == 2) {
+    if constexpr ((KIND == KIND_PRIMAL || KIND == KIND_SIB) && STAGE == 2) {
         if (blockIdx.x == 0 && blockIdx.z == 0 && threadIdx.x == 0) a.step[0] += 1;
     }
 }
@@ -700,7 +760,7 @@ __global__ __launch_bounds__(64 * WMW * WNW) void heun_stage_grouped(const GemmA
         __syncthreads();   // LDS of the previous tile is free
         stage_tile<PREC, MT, NT, KB, WMW, WNW, NST, STAGE, KIND>(args[tt.x], tt.y, tt.z, tt.w);
     }
-    if constexpr (KIND == KIND_PRIMAL && STAGE == 2) {
+    if constexpr ((KIND == KIND_PRIMAL || KIND == KIND_SIB) && STAGE == 2) {
         if (blockIdx.x == 0 && threadIdx.x == 0) step[0] += 1;
     }
 }
@@ -757,6 +817,7 @@ static int dispatch_kind(const GemmArgs<PREC>& a, int stage, int kind, int64_t P
     if (stage == 1) {
         switch (kind) {
             case KIND_PRIMAL: return launch_kernel<PREC, CFG, 1, KIND_PRIMAL>(a, P, C2, ncopy, st);
+            case KIND_SIB: return launch_kernel<PREC, CFG, 1, KIND_SIB>(a, P, C2, ncopy, st);
             case KIND_TANGENT: return launch_kernel<PREC, CFG, 1, KIND_TANGENT>(a, P, C2, ncopy, st);
             case KIND_STORE: return launch_kernel<PREC, CFG, 1, KIND_STORE>(a, P, C2, ncopy, st);
             case KIND_ADJ1: return launch_kernel<PREC, CFG, 1, KIND_ADJ1>(a, P, C2, ncopy, st);
@@ -764,6 +825,7 @@ static int dispatch_kind(const GemmArgs<PREC>& a, int stage, int kind, int64_t P
     } else {
         switch (kind) {
             case KIND_PRIMAL: return launch_kernel<PREC, CFG, 2, KIND_PRIMAL>(a, P, C2, ncopy, st);
+            case KIND_SIB: return launch_kernel<PREC, CFG, 2, KIND_SIB>(a, P, C2, ncopy, st);
             case KIND_TANGENT: return launch_kernel<PREC, CFG, 2, KIND_TANGENT>(a, P, C2, ncopy, st);
             case KIND_ADJ2: return launch_kernel<PREC, CFG, 2, KIND_ADJ2>(a, P, C2, ncopy, st);
         }
@@ -870,7 +932,8 @@ template <int PREC>
 static int launch_gemm_p(const Geometry& g, const EnsembleBuffers& b, const StepConsts& c, int stage,
                          bool tangent, int cur, bool store_y2, bool keep_dlt, hipStream_t st) {
     const GemmArgs<PREC> a = make_args<PREC>(g, b, c, stage, tangent, cur, store_y2, keep_dlt);
-    return dispatch_cfg<PREC>(a, g.cfg, stage, tangent ? KIND_TANGENT : KIND_PRIMAL, g.P, g.C2, tangent ? 2 : 1,
+    const int kind = tangent ? KIND_TANGENT : g.integrator == TWA_INT_SIB ? KIND_SIB : KIND_PRIMAL;
+    return dispatch_cfg<PREC>(a, g.cfg, stage, kind, g.P, g.C2, tangent ? 2 : 1,
                               st);
 }
 
@@ -955,15 +1018,21 @@ int launch_gemm_call(const Geometry& g, const GemmCall& c, hipStream_t st) {
 
 // ---------------------------------------------------------------------------
 // grouped persistent launches of many ensembles (batched parameter scan)
-template <int PREC, int CFG, int STAGE>
-static int grouped_launch_t(const GroupedPlan& pl, int cur, hipStream_t st) {
+template <int PREC, int CFG, int STAGE, int KIND>
+static int grouped_launch_k(const GroupedPlan& pl, int cur, hipStream_t st) {
     typedef CfgT<PREC, CFG> C;
-    hipLaunchKernelGGL((heun_stage_grouped<PREC, C::MT, C::NT, C::KB, C::WMW, C::WNW, C::NST, STAGE, KIND_PRIMAL>),
+    hipLaunchKernelGGL((heun_stage_grouped<PREC, C::MT, C::NT, C::KB, C::WMW, C::WNW, C::NST, STAGE, KIND>),
                        dim3((unsigned)pl.grid), dim3(64 * C::WMW * C::WNW), 0, st,
                        static_cast<const GemmArgs<PREC>*>(pl.d_args[STAGE - 1][cur]), pl.d_tiles[STAGE - 1],
                        pl.ntiles[STAGE - 1], pl.step);
     TWA_HIP_CHECK(hipGetLastError());
     return TWA_OK;
+}
+
+template <int PREC, int CFG, int STAGE>
+static int grouped_launch_t(const GroupedPlan& pl, int cur, hipStream_t st) {
+    return pl.integrator == TWA_INT_SIB ? grouped_launch_k<PREC, CFG, STAGE, KIND_SIB>(pl, cur, st)
+                                        : grouped_launch_k<PREC, CFG, STAGE, KIND_PRIMAL>(pl, cur, st);
 }
 
 template <int PREC, int CFG>
@@ -1013,6 +1082,9 @@ static int grouped_prepare_p(const std::vector<Geometry>& gs, const std::vector<
         case 1: occ = grouped_occupancy<PREC, 1>(1); break;
         case 2: occ = grouped_occupancy<PREC, 2>(1); break;
         case 3: occ = grouped_occupancy<PREC, 3>(1); break;
+        case 7:
+            if constexpr (PREC != TWA_PREC_FP64) occ = grouped_occupancy<PREC, 7>(1);
+            break;
         default: break;
     }
     // tile list: (point, M tile, column tile, 0), longest contraction first
@@ -1046,6 +1118,7 @@ static int grouped_prepare_p(const std::vector<Geometry>& gs, const std::vector<
     pl.grid = grid;
     pl.cfg = cfg;
     pl.precision = PREC;
+    pl.integrator = gs[0].integrator;
     pl.step = step;
     return TWA_OK;
 }
@@ -1070,8 +1143,11 @@ static int grouped_launch_p(const GroupedPlan& pl, int stage, int cur, hipStream
         case 1: return grouped_dispatch<PREC, 1>(pl, stage, cur, st);
         case 2: return grouped_dispatch<PREC, 2>(pl, stage, cur, st);
         case 3: return grouped_dispatch<PREC, 3>(pl, stage, cur, st);
+        case 7:
+            if constexpr (PREC != TWA_PREC_FP64) return grouped_dispatch<PREC, 7>(pl, stage, cur, st);
+            break;
     }
-    set_error("grouped launch: tile configuration must be 0..3");
+    set_error("grouped launch: tile configuration must be 0..3 or 7 (not 7 in FP64)");
     return TWA_EINVAL;
 }
 
