@@ -51,6 +51,8 @@ extern "C" {
                             /* a non-PSD dense matrix)                         */
 #define TWA_EUNSTABLE  -5   /* NaN/Inf in the state or accumulators; outputs   */
                             /* are still written so they can be inspected      */
+#define TWA_ENOROOT    -6   /* threshold search: the objective does not cross  */
+                            /* the target on the bracket, or no convergence    */
 
 /* ---- precisions of the channel-mixing contraction ---------------------- */
 #define TWA_PREC_FP64   0   /* FP64 state, FP64 MFMA contraction               */
@@ -269,6 +271,78 @@ TWA_API int twa_run_batch(const twa_point* pts, int n_points, const twa_batch_op
 TWA_API int twa_adjoint(const twa_params* p, int64_t n_traj, double dt, int64_t n_steps,
                         uint64_t seed, int32_t ckpt_every, twa_observables* out,
                         double* grads);
+
+/* ======================================================================
+ * The paper's protocol and threshold quantities.
+ * ====================================================================== */
+/* Objectives of the threshold search (main text, results): the coherent-light
+ * cutoff g2 = 1.08 at fixed N and the superradiant intensity <S+S-> = N. */
+#define TWA_OBJ_G2       0   /* g2 of the steady state                            */
+#define TWA_OBJ_SPSM_N   1   /* <S+S-> / N of the steady state                    */
+
+typedef struct {
+    double dt;               /* cfl / max(Gamma N, lambda_max): the step criterion of
+                                the main text's methods paragraph (< 0.05)          */
+    double tau_s;            /* preparation time: 10/Gamma for alpha < 1, 10/lambda_min
+                                for alpha >= 1 (main text); with finite_size,
+                                10 / [w (2 eta(alpha) - 1)] (SM Sec. S1)            */
+    double tau;              /* averaging window 5/Gamma                           */
+    int64_t n_prep;          /* ceil(tau_s / dt - 1e-9): burn-in steps              */
+    int64_t n_window;        /* ceil(tau / dt - 1e-9): window steps                 */
+    double wt;               /* normalised pump lambda_max / (Gamma N)              */
+    double lam_min, lam_max; /* channel rates of the pump                          */
+} twa_protocol_t;
+
+/*
+ * twa_protocol -- the protocol of one point of the paper's scans for a pump
+ * from twa_build_pump (finite_size also needs its w and alpha; eta is the
+ * Dirichlet eta function, computed by Borwein's alternating-series method).
+ * cfl must be in (0, 0.05).  Errors: TWA_EINVAL (null pointers, gamma <= 0,
+ * cfl outside (0, 0.05), finite_size with 2 eta(alpha) - 1 <= 0 or a dense
+ * pump).
+ */
+TWA_API int twa_protocol(const twa_pump* pump, double gamma, double cfl, int32_t finite_size,
+                         twa_protocol_t* out);
+
+typedef struct {
+    int32_t objective;       /* TWA_OBJ_G2 or TWA_OBJ_SPSM_N                       */
+    double target;           /* e.g. 1.08 for g2, 1.0 for <S+S->/N                 */
+    double w_lo, w_hi;       /* bracket of the pump amplitude w of Eq. (2),
+                                0 < w_lo < w_hi, objective - target changing sign  */
+    double tol_w;            /* stop once the Newton correction is below tol_w      */
+    int32_t max_iter;        /* gradient evaluations at most (each one twa_adjoint) */
+    int32_t ckpt_every;      /* checkpoint interval of twa_adjoint                  */
+} twa_threshold_opts;
+
+TWA_API void twa_threshold_opts_default(twa_threshold_opts* o);
+
+/*
+ * twa_find_threshold -- the pump amplitude w at which the fixed-noise
+ * steady-state objective of twa_run (same seed for every w, so the
+ * objective is a smooth function of w) equals o->target, by Newton steps
+ * with the pathwise derivative of twa_adjoint, kept inside a bracket that
+ * is bisected whenever a Newton step leaves it.  The pump is factorised once
+ * (at w_hi); other amplitudes scale it exactly (W ~ w, F ~ sqrt(w)).  p gives
+ * gamma, s0z, burnin, precision, point and tile_config; p->pump is ignored.
+ * Outputs: *w_root, *f_root = objective(w_root) - target, *n_iter = gradient
+ * evaluations used (any output pointer may be NULL).  Errors as twa_adjoint;
+ * TWA_ENOROOT if the bracket has no sign change or max_iter is reached.
+ */
+TWA_API int twa_find_threshold(int64_t N, double alpha, const twa_params* p, int64_t n_traj, double dt,
+                               int64_t n_steps, uint64_t seed, const twa_threshold_opts* o, double* w_root,
+                               double* f_root, int32_t* n_iter);
+
+/*
+ * twa_g2_min -- the g2_min protocol of the paper (main text, results): g2 at
+ * n_points equally spaced normalised pumps w~ in [wt_lo, wt_hi], every point
+ * run with its own twa_protocol (n_prep burn-in steps + n_window averaged
+ * steps, same seed), and the smallest of them.  wt_out[n_points] and
+ * g2_out[n_points] (host, may be NULL) receive the curve.  p as in
+ * twa_find_threshold.  Errors as twa_run and twa_protocol.
+ */
+TWA_API int twa_g2_min(int64_t N, double alpha, const twa_params* p, int64_t n_traj, uint64_t seed,
+                       int32_t n_points, double wt_lo, double wt_hi, double cfl, int32_t finite_size,
+                       double* wt_out, double* g2_out, double* wt_min, double* g2_min);
 
 /* ======================================================================
  * Kernel-level entry points used by the parity tests.

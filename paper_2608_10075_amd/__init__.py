@@ -73,6 +73,16 @@ class _BatchOpts(C.Structure):
                 ("integrator", C.c_int32)]
 
 
+class _Protocol(C.Structure):
+    _fields_ = [("dt", C.c_double), ("tau_s", C.c_double), ("tau", C.c_double), ("n_prep", C.c_int64),
+                ("n_window", C.c_int64), ("wt", C.c_double), ("lam_min", C.c_double), ("lam_max", C.c_double)]
+
+
+class _ThresholdOpts(C.Structure):
+    _fields_ = [("objective", C.c_int32), ("target", C.c_double), ("w_lo", C.c_double), ("w_hi", C.c_double),
+                ("tol_w", C.c_double), ("max_iter", C.c_int32), ("ckpt_every", C.c_int32)]
+
+
 def load_library(path: str = LIB_PATH) -> C.CDLL:
     if not os.path.exists(path):
         raise ImportError("libtwa.so is not built (run __graft_entry__.build()); no CPU fallback exists")
@@ -97,8 +107,18 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
                                 C.POINTER(_Obs), C.POINTER(C.c_double)]
     lib.twa_philox.argtypes = [P, C.c_int64, C.c_uint32, C.c_uint32, P, P]
     lib.twa_noise.argtypes = [C.c_uint64, C.c_int64, C.c_int32, C.c_int64, C.c_int64, C.c_int32, P, P, P]
+    lib.twa_protocol.argtypes = [P, C.c_double, C.c_double, C.c_int32, C.POINTER(_Protocol)]
+    lib.twa_threshold_opts_default.argtypes = [C.POINTER(_ThresholdOpts)]
+    lib.twa_threshold_opts_default.restype = None
+    lib.twa_find_threshold.argtypes = [C.c_int64, C.c_double, C.POINTER(_Params), C.c_int64, C.c_double, C.c_int64,
+                                       C.c_uint64, C.POINTER(_ThresholdOpts), C.POINTER(C.c_double),
+                                       C.POINTER(C.c_double), C.POINTER(C.c_int32)]
+    lib.twa_g2_min.argtypes = [C.c_int64, C.c_double, C.POINTER(_Params), C.c_int64, C.c_uint64, C.c_int32,
+                               C.c_double, C.c_double, C.c_double, C.c_int32, C.POINTER(C.c_double),
+                               C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double)]
     for name in ("twa_build_pump", "twa_build_pump_dense", "twa_pump_info", "twa_pump_copy_matrix", "twa_run",
-                 "twa_run_batch", "twa_adjoint", "twa_philox", "twa_noise"):
+                 "twa_run_batch", "twa_adjoint", "twa_philox", "twa_noise", "twa_protocol", "twa_find_threshold",
+                 "twa_g2_min"):
         getattr(lib, name).restype = C.c_int
     return lib
 
@@ -280,6 +300,62 @@ def adjoint(pump: Pump, n_traj: int, dt: float, n_steps: int, seed: int = 0, *, 
     _check(_lib.twa_adjoint(C.byref(p), int(n_traj), float(dt), int(n_steps), C.c_uint64(seed & (2 ** 64 - 1)),
                             int(ckpt_every), C.byref(o), g))
     return _obs_dict(o), dict(zip(GRAD_NAMES, list(g)))
+
+
+OBJECTIVES = {"g2": 0, "spsm_n": 1}
+
+
+def _base_params(gamma, s0z, burnin, precision, point, tile_config, stream):
+    p = _Params()
+    _lib.twa_params_default(C.byref(p))
+    p.gamma, p.s0z, p.burnin = gamma, s0z, burnin
+    p.precision = PRECISIONS[precision]
+    p.point, p.tile_config = point, tile_config
+    p.stream = _stream_ptr(stream)
+    return p
+
+
+def protocol(pump: Pump, gamma: float = 1.0, cfl: float = 0.04, finite_size: bool = False) -> dict:
+    """twa_protocol: time step, preparation time, window and step counts of the
+    paper's protocol for one pump."""
+    o = _Protocol()
+    _check(_lib.twa_protocol(pump.handle, float(gamma), float(cfl), 1 if finite_size else 0, C.byref(o)))
+    return {k: getattr(o, k) for k, _ in _Protocol._fields_}
+
+
+def find_threshold(N: int, alpha: float, n_traj: int, dt: float, n_steps: int, seed: int = 0, *,
+                   objective: str = "g2", target: float = 1.08, w_lo: float, w_hi: float, tol_w: float = 1e-6,
+                   max_iter: int = 30, ckpt_every: int = 256, gamma: float = 1.0, s0z: float = 1.0,
+                   burnin: int = -1, precision: str = "fp32", point: int = 0, tile_config: int = -1, stream=None):
+    """twa_find_threshold: the pump amplitude w where the fixed-noise objective
+    ("g2" or "spsm_n" = <S+S->/N) equals target; returns (w, objective - target,
+    gradient evaluations)."""
+    p = _base_params(gamma, s0z, burnin, precision, point, tile_config, stream)
+    o = _ThresholdOpts()
+    _lib.twa_threshold_opts_default(C.byref(o))
+    o.objective, o.target, o.w_lo, o.w_hi = OBJECTIVES[objective], target, w_lo, w_hi
+    o.tol_w, o.max_iter, o.ckpt_every = tol_w, max_iter, ckpt_every
+    w, f, it = C.c_double(), C.c_double(), C.c_int32()
+    _check(_lib.twa_find_threshold(int(N), float(alpha), C.byref(p), int(n_traj), float(dt), int(n_steps),
+                                   C.c_uint64(seed & (2 ** 64 - 1)), C.byref(o), C.byref(w), C.byref(f),
+                                   C.byref(it)))
+    return w.value, f.value, it.value
+
+
+def g2_min(N: int, alpha: float, n_traj: int, seed: int = 0, *, n_points: int = 10, wt_lo: float = 0.1,
+           wt_hi: float = 1.0, cfl: float = 0.04, finite_size: bool = False, gamma: float = 1.0,
+           s0z: float = 1.0, precision: str = "fp32", point: int = 0, tile_config: int = -1, stream=None):
+    """twa_g2_min: g2 over n_points equally spaced w~ in [wt_lo, wt_hi], each point
+    with its own protocol; returns (w~ array, g2 array, w~ of the minimum, g2_min)."""
+    p = _base_params(gamma, s0z, -1, precision, point, tile_config, stream)
+    wt = np.zeros(n_points)
+    g2 = np.zeros(n_points)
+    wmin, gmin = C.c_double(), C.c_double()
+    _check(_lib.twa_g2_min(int(N), float(alpha), C.byref(p), int(n_traj), C.c_uint64(seed & (2 ** 64 - 1)),
+                           int(n_points), float(wt_lo), float(wt_hi), float(cfl), 1 if finite_size else 0,
+                           wt.ctypes.data_as(C.POINTER(C.c_double)), g2.ctypes.data_as(C.POINTER(C.c_double)),
+                           C.byref(wmin), C.byref(gmin)))
+    return wt, g2, wmin.value, gmin.value
 
 
 def philox(ctr: np.ndarray, key0: int, key1: int) -> np.ndarray:

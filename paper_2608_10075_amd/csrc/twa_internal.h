@@ -158,7 +158,8 @@ int launch_philox(const uint32_t* ctr, int64_t n, uint32_t k0, uint32_t k1, uint
 int launch_noise_debug(uint64_t seed, int64_t step, int32_t point, int64_t B, int64_t N, int fp64,
                        double* zeta, double* g, hipStream_t st);
 
-// pump (twa_pump.hip)
+// pump (twa_pump.hip): the Eq. (2) pump of a handle rescaled to amplitude w
+int pump_scaled(const twa_pump* base, double w, twa_pump** out);
 }  // namespace twa
 
 struct twa_pump {

@@ -145,6 +145,56 @@ static void pump_release(twa_pump* p) {
     delete p;
 }
 
+__global__ void scale_kernel(int64_t n, const double* in, double f, double* out) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) out[t] = f * in[t];
+}
+
+// The pump of Eq. (2) at amplitude w from one at amplitude w0 > 0 with the
+// same alpha: W is linear in w and its PSD square root scales with sqrt(w),
+// the eigenvectors are unchanged and the eigenvalues scale with w.
+int pump_scaled(const twa_pump* b, double w, twa_pump** out) {
+    if (!b || !out || !(b->w > 0) || !std::isfinite(b->w) || !(w > 0) || !std::isfinite(w) || !b->V || !b->lam) {
+        set_error("pump_scaled: needs a pump from twa_build_pump with w > 0 and a target w > 0");
+        return TWA_EINVAL;
+    }
+    const int64_t N = b->N, n2 = N * N;
+    const double f = w / b->w;
+    twa_pump* p = new twa_pump();
+    p->N = N;
+    p->w = w;
+    p->alpha = b->alpha;
+    p->lam_min = f * b->lam_min;
+    p->lam_max = f * b->lam_max;
+    p->device = b->device;
+    const size_t bytes = (size_t)n2 * sizeof(double);
+    if (hipMalloc(&p->W, bytes) != hipSuccess || hipMalloc(&p->F, bytes) != hipSuccess ||
+        hipMalloc(&p->V, bytes) != hipSuccess) {
+        pump_release(p);
+        set_error("pump_scaled: device allocation failed");
+        return TWA_ENOMEM;
+    }
+    p->lam = (double*)malloc((size_t)N * sizeof(double));
+    if (!p->lam) {
+        pump_release(p);
+        set_error("pump_scaled: host allocation failed");
+        return TWA_ENOMEM;
+    }
+    for (int64_t j = 0; j < N; ++j) p->lam[j] = f * b->lam[j];
+    const unsigned nb = (unsigned)((n2 + 255) / 256);
+    hipLaunchKernelGGL(scale_kernel, dim3(nb), dim3(256), 0, 0, n2, b->W, f, p->W);
+    hipLaunchKernelGGL(scale_kernel, dim3(nb), dim3(256), 0, 0, n2, b->F, std::sqrt(f), p->F);
+    if (hipGetLastError() != hipSuccess ||
+        hipMemcpy(p->V, b->V, bytes, hipMemcpyDeviceToDevice) != hipSuccess ||
+        hipDeviceSynchronize() != hipSuccess) {
+        pump_release(p);
+        set_error("pump_scaled: scaling failed");
+        return TWA_EHIP;
+    }
+    *out = p;
+    return TWA_OK;
+}
+
 }  // namespace twa
 
 extern "C" {
