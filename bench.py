@@ -99,27 +99,34 @@ def cpu_baseline(N, w, alpha, dt, budget_s=15.0):
 
 
 def adjoint_cost(twa, steps=2048, reps=1):
-    """Wall time of twa_adjoint (forward with checkpoints + reverse sweep)
-    divided by the wall time of twa_run on the same configuration."""
+    """Wall time of twa_adjoint (forward with checkpoints + reverse sweep) for
+    dg2/d(w, alpha) divided by the wall time of twa_run on the same
+    configuration; also the cost with both objectives (<S+S-> and g2) swept."""
     import torch
     N, B, w, alpha, dt, ck = 2000, 2048, 2.0, 1.0, 1e-4, 256
     pump = twa.build_pump(N, w, alpha)
     twa.run(pump, B, dt, 64, seed=0, precision="fp32")           # warm caches / graphs
-    twa.adjoint(pump, B, dt, 256, seed=0, precision="fp32", ckpt_every=ck)
-    fwd, adj = [], []
+    twa.adjoint(pump, B, dt, 256, seed=0, precision="fp32", ckpt_every=ck, objectives=("g2",))
+    fwd, adj, adj2 = [], [], []
     for _ in range(reps):
         torch.cuda.synchronize()
         t0 = time.time()
         r = twa.run(pump, B, dt, steps, seed=0, precision="fp32")
         torch.cuda.synchronize()
         t1 = time.time()
-        obs, grads = twa.adjoint(pump, B, dt, steps, seed=0, precision="fp32", ckpt_every=ck)
+        obs, grads = twa.adjoint(pump, B, dt, steps, seed=0, precision="fp32", ckpt_every=ck, objectives=("g2",))
         torch.cuda.synchronize()
         t2 = time.time()
+        twa.adjoint(pump, B, dt, steps, seed=0, precision="fp32", ckpt_every=ck)
+        torch.cuda.synchronize()
+        t3 = time.time()
         fwd.append(t1 - t0)
         adj.append(t2 - t1)
-    f, a = min(fwd), min(adj)
-    return {"ratio": a / f, "forward_s": f, "adjoint_s": a, "steps": steps,
+        adj2.append(t3 - t2)
+    f, a, a2 = min(fwd), min(adj), min(adj2)
+    grads = {k: v for k, v in grads.items() if k.startswith("d_g2")}
+    return {"ratio": a / f, "forward_s": f, "adjoint_s": a, "steps": steps, "objective": "g2",
+            "ratio_both_objectives": a2 / f,
             "config": {"N": N, "alpha": alpha, "w": w, "n_traj": B, "dt": dt, "precision": "fp32",
                        "ckpt_every": ck, "tile_config": r.obs["tile_config"]},
             "forward_ms_per_step": 1e3 * f / steps, "adjoint_ms_per_step": 1e3 * a / steps,

@@ -139,11 +139,14 @@ typedef struct twa_params {
     int32_t use_graph;       /* 1: replay the step loop from captured hipGraphs    */
     double kappa;            /* weight of the response (commutator) part in the    */
                              /* two-time correlation; default 1/4                  */
+    int32_t adjoint_objectives; /* twa_adjoint: mask of 1 (<S+S->) and 2 (g2); 0 =  */
+                             /* both.  The reverse sweep carries one copy per       */
+                             /* objective; unselected gradients are returned NaN   */
 } twa_params;
 
 /* Fills *p with defaults: gamma 1, s0z +1, burnin -1, Heun, FP32, no lags,
  * point 0, automatic tiles, null stream, no initial state, no per-launch
- * timing, hipGraph replay on, kappa 1/4. */
+ * timing, hipGraph replay on, kappa 1/4, both adjoint objectives. */
 TWA_API void twa_params_default(twa_params* p);
 
 typedef struct twa_observables {

@@ -38,7 +38,7 @@ class _Params(C.Structure):
                 ("integrator", C.c_int32), ("precision", C.c_int32), ("n_lags", C.c_int64),
                 ("lag_stride", C.c_int64), ("point", C.c_int32), ("tile_config", C.c_int32),
                 ("stream", C.c_void_p), ("init_state", C.POINTER(C.c_double)), ("timing", C.c_int32),
-                ("use_graph", C.c_int32), ("kappa", C.c_double)]
+                ("use_graph", C.c_int32), ("kappa", C.c_double), ("adjoint_objectives", C.c_int32)]
 
 
 _OBS_DOUBLES1 = ["T2", "T3", "T4", "Z", "ZZ", "Sz", "SpSm", "g2",
@@ -285,12 +285,16 @@ GRAD_NAMES = ("d_SpSm_dw", "d_SpSm_dalpha", "d_g2_dw", "d_g2_dalpha")
 
 def adjoint(pump: Pump, n_traj: int, dt: float, n_steps: int, seed: int = 0, *, ckpt_every: int = 256,
             gamma: float = 1.0, s0z: float = 1.0, burnin: int = -1, precision: str = "fp32", point: int = 0,
-            tile_config: int = -1, stream=None):
+            tile_config: int = -1, stream=None, objectives=("SpSm", "g2")):
     """twa_adjoint: observables of the forward run and the pathwise gradients
-    d<S+S->/dw, d<S+S->/dalpha, dg2/dw, dg2/dalpha at fixed noise."""
+    d<S+S->/dw, d<S+S->/dalpha, dg2/dw, dg2/dalpha at fixed noise (those of
+    objectives not requested are NaN; each objective costs one reverse copy)."""
     p = _Params()
     _lib.twa_params_default(C.byref(p))
     p.pump = pump.handle
+    p.adjoint_objectives = (1 if "SpSm" in objectives else 0) | (2 if "g2" in objectives else 0)
+    if p.adjoint_objectives == 0:
+        raise ValueError("objectives must contain 'SpSm' and/or 'g2'")
     p.gamma, p.s0z, p.burnin = gamma, s0z, burnin
     p.precision = PRECISIONS[precision]
     p.point, p.tile_config = point, tile_config

@@ -123,9 +123,9 @@ __global__ __launch_bounds__(256) void prep_nu2_kernel(const typename Prec<PREC>
 template <typename S>
 __global__ void src_init_kernel(const S* part, int64_t N, int64_t B, int64_t P, int64_t Bp, int64_t nmt, S c00,
                                 S c01, S c02, S c03, S c04, S c10, S c11, S c12, S c13, S c14, S scale, int on,
-                                S* lam) {
+                                int64_t ncopy, S* lam) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= 2 * Bp * P) return;
+    if (t >= ncopy * Bp * P) return;
     const int cp = (int)(t / (Bp * P));
     const int64_t r = t % (Bp * P), k = r / P, i = r % P, SP = Bp * P;
     S ox = 0, oy = 0, oz = 0;
@@ -159,10 +159,10 @@ int state_to_op(const Geometry& g, const void* s, void* Xop, hipStream_t st) {
 }
 
 template <int PREC>
-int prep_nu2(const Geometry& g, const void* lam, const void* s, const void* d, void* op, void* part,
+int prep_nu2(const Geometry& g, const void* lam, const void* s, const void* d, void* op, void* part, int ncopy,
              hipStream_t st) {
     typedef typename Prec<PREC>::S S;
-    dim3 grid(nblk(g.Bp, 4), (unsigned)g.nmt, 2);
+    dim3 grid(nblk(g.Bp, 4), (unsigned)g.nmt, (unsigned)ncopy);
     hipLaunchKernelGGL(prep_nu2_kernel<PREC>, grid, dim3(256), 0, st, static_cast<const S*>(lam),
                        static_cast<const S*>(s), static_cast<const S*>(d), g.P, g.Bp, g.nmt, g.P / g.nmt, g.C2,
                        static_cast<typename Prec<PREC>::G*>(op), static_cast<S*>(part));
@@ -172,12 +172,12 @@ int prep_nu2(const Geometry& g, const void* lam, const void* s, const void* d, v
 
 template <int PREC>
 int src_init(const Geometry& g, const void* part, const double (*cf)[5], double scale, int on, void* lam,
-             hipStream_t st) {
+             int ncopy, hipStream_t st) {
     typedef typename Prec<PREC>::S S;
-    hipLaunchKernelGGL(src_init_kernel<S>, dim3(nblk(2 * g.Bp * g.P, 256)), dim3(256), 0, st,
+    hipLaunchKernelGGL(src_init_kernel<S>, dim3(nblk((int64_t)ncopy * g.Bp * g.P, 256)), dim3(256), 0, st,
                        static_cast<const S*>(part), g.N, g.B, g.P, g.Bp, g.nmt, (S)cf[0][0], (S)cf[0][1],
                        (S)cf[0][2], (S)cf[0][3], (S)cf[0][4], (S)cf[1][0], (S)cf[1][1], (S)cf[1][2], (S)cf[1][3],
-                       (S)cf[1][4], (S)scale, on, static_cast<S*>(lam));
+                       (S)cf[1][4], (S)scale, on, (int64_t)ncopy, static_cast<S*>(lam));
     TWA_HIP_CHECK(hipGetLastError());
     return TWA_OK;
 }
@@ -292,6 +292,11 @@ int adjoint_impl(const twa_params* p, int64_t n_traj, double dt, int64_t n_steps
     const Geometry g = make_geometry(p->precision, cfg, N, B);
     const int J = (int)std::min<int64_t>(32, B);
     const int64_t nseg = (n_steps + K - 1) / K;
+    // objectives carried by the reverse sweep (0 = <S+S->, 1 = g2), one copy each
+    const int mask = p->adjoint_objectives == 0 ? 3 : p->adjoint_objectives;
+    int obj[2] = {0, 1}, nobj = 0;
+    if (mask & 1) obj[nobj++] = 0;
+    if (mask & 2) obj[nobj++] = 1;
     const size_t se = sizeof(S), ge = (size_t)gemm_elt_bytes(p->precision);
     const size_t plane = (size_t)g.Bp * g.P * se;
     const size_t partsz = (size_t)3 * g.nmt * g.Bp * se;
@@ -437,15 +442,16 @@ int adjoint_impl(const twa_params* p, int64_t n_traj, double dt, int64_t n_steps
         const double a2 = 1.0 / (den * den), a3 = num / (den * den * den);
         const double c0[5] = {1.0, 0.0, 0.0, 0.5, 0.0};
         const double c1_[5] = {-(4.0 / 3.0) * a2 - 2.0 * a3, 2.0 * a2, a2, -a2 / 3.0 - a3, 0.5 * a2};
+        // copies of the reverse sweep: both objectives, or the selected one in copy 0
         for (int q = 0; q < 5; ++q) {
-            cf[0][q] = c0[q];
-            cf[1][q] = c1_[q];
+            cf[0][q] = obj[0] == 0 ? c0[q] : c1_[q];
+            cf[1][q] = nobj == 2 ? c1_[q] : 0.0;
         }
         scale = 1.0 / ((double)B * (double)ns);
     }
 
     // ---------------- backward
-    TWA_TRY(src_init<PREC>(g, b.part[0], cf, scale, n_steps > burnin ? 1 : 0, m.lam, st));
+    TWA_TRY(src_init<PREC>(g, b.part[0], cf, scale, n_steps > burnin ? 1 : 0, m.lam, nobj, st));
     for (int64_t q = nseg - 1; q >= 0; --q) {
         const int64_t n0 = q * K, len = std::min<int64_t>(K, n_steps - n0);
         // recompute the segment from its checkpoint
@@ -471,15 +477,12 @@ int adjoint_impl(const twa_params* p, int64_t n_traj, double dt, int64_t n_steps
             EnsembleBuffers bj = b;
             bj.g = gj;
             TWA_TRY(launch_noise(g, bj, c, st));
-            GemmCall p1;
-            p1.kind = 0; p1.stage = 1; p1.A = b.A; p1.lda = 2 * g.P; p1.X = b.Xop; p1.ldx = 2 * g.P; p1.K = 2 * g.P;
-            p1.c1 = c.c1; p1.c2 = c.c2; p1.s_cur = sj; p1.dlt = dj; p1.Y = y1j; p1.Dop = b.Dop;
+            GemmCall p1;   // predictor, also storing its noise part Q = -sqrt(dt) F zeta (second K half)
+            p1.kind = KIND_PRIMAL_WITH_Q; p1.stage = 1; p1.A = b.A; p1.lda = 2 * g.P; p1.X = b.Xop;
+            p1.ldx = 2 * g.P; p1.K = 2 * g.P;
+            p1.c1 = c.c1; p1.c2 = c.c2; p1.s_cur = sj; p1.dlt = dj; p1.Y = y1j; p1.Dop = b.Dop; p1.Sout = qj;
             p1.part_prim = pSj; p1.part_out = pPj; p1.g = gj; p1.step = b.step;
             TWA_TRY(launch_gemm_call(g, p1, st));
-            GemmCall sq;   // Q = Y1 - A_left s
-            sq.kind = 2; sq.stage = 1; sq.A = b.A; sq.lda = 2 * g.P; sq.X = b.Xop; sq.ldx = 2 * g.P; sq.K = g.P;
-            sq.Sin = y1j; sq.Sout = qj; sq.store_sign = -1.0;
-            TWA_TRY(launch_gemm_call(g, sq, st));
             GemmCall sa1;  // dY1/dalpha = A_alpha [s; zeta]
             sa1.kind = 2; sa1.stage = 1; sa1.A = m.Aa; sa1.lda = 2 * g.P; sa1.X = b.Xop; sa1.ldx = 2 * g.P;
             sa1.K = 2 * g.P; sa1.Sout = ya1j; sa1.store_sign = 1.0;
@@ -508,16 +511,16 @@ int adjoint_impl(const twa_params* p, int64_t n_traj, double dt, int64_t n_steps
             char* pSj = (char*)m.partS + (size_t)j * partsz;
             char* pPj = (char*)m.partP + (size_t)j * partsz;
             char* gj = (char*)m.g + (size_t)j * 2 * g.Bp * se;
-            TWA_TRY(prep_nu2<PREC>(g, m.lam, sj, dj, m.nu2, m.nu2p, st));
+            TWA_TRY(prep_nu2<PREC>(g, m.lam, sj, dj, m.nu2, m.nu2p, nobj, st));
             GemmCall a2;
-            a2.kind = 3; a2.stage = 2; a2.ncopy = 2; a2.A = b.A; a2.lda = 2 * g.P; a2.X = m.nu2; a2.ldx = g.P;
+            a2.kind = 3; a2.stage = 2; a2.ncopy = nobj; a2.A = b.A; a2.lda = 2 * g.P; a2.X = m.nu2; a2.ldx = g.P;
             a2.x_copy = g.C2 * g.P; a2.K = g.P; a2.c1 = c.c1; a2.c2 = c.c2; a2.s_cur = sj; a2.dlt = dj; a2.Y = y1j;
             a2.Y2in = y2j; a2.Qin = qj; a2.YA = ya2j; a2.lam = m.lam; a2.M1 = m.M1; a2.Rb = m.Rb;
             a2.part_prim = pPj; a2.g = gj; a2.tpart_in = m.nu2p; a2.part_out = m.nu1p; a2.Xnext = m.nu1;
             a2.ldxn = g.P; a2.gacc = m.gacc; a2.inv_w = 1.0 / pump->w;
             TWA_TRY(launch_gemm_call(g, a2, st));
             GemmCall a1;
-            a1.kind = 4; a1.stage = 1; a1.ncopy = 2; a1.A = b.A; a1.lda = 2 * g.P; a1.X = m.nu1; a1.ldx = g.P;
+            a1.kind = 4; a1.stage = 1; a1.ncopy = nobj; a1.A = b.A; a1.lda = 2 * g.P; a1.X = m.nu1; a1.ldx = g.P;
             a1.x_copy = g.C2 * g.P; a1.K = g.P; a1.c1 = c.c1; a1.c2 = c.c2; a1.s_cur = sj; a1.Y = y1j; a1.Qin = qj;
             a1.YA = ya1j; a1.lam = m.lam; a1.M1 = m.M1; a1.Rb = m.Rb; a1.part_prim = pSj; a1.g = gj;
             a1.tpart_in = m.nu1p; a1.gacc = m.gacc; a1.inv_w = 1.0 / pump->w;
@@ -533,12 +536,13 @@ int adjoint_impl(const twa_params* p, int64_t n_traj, double dt, int64_t n_steps
     TWA_HTRY(hipStreamSynchronize(st));
     TWA_HTRY(hipEventElapsedTime(&fwd_ms, e0, e1));
     TWA_HTRY(hipEventElapsedTime(&bwd_ms, e1, e2));
-    for (int cp = 0; cp < 2; ++cp)
+    for (int q = 0; q < 4; ++q) grads[q] = NAN;
+    for (int cp = 0; cp < nobj; ++cp)
         for (int prm = 0; prm < 2; ++prm) {
             double s = 0;
             const size_t base = ((size_t)cp * 2 + prm) * g.nmt * g.Bp;
             for (size_t t = 0; t < (size_t)g.nmt * g.Bp; ++t) s += hg[base + t];
-            grads[cp * 2 + prm] = s;
+            grads[obj[cp] * 2 + prm] = s;
         }
     out->kernel_ms = fwd_ms + bwd_ms;
     out->adjoint_fwd_ms = fwd_ms;
@@ -575,6 +579,10 @@ extern "C" TWA_API int twa_adjoint(const twa_params* p, int64_t n_traj, double d
     }
     if (p->integrator != TWA_INT_HEUN) {
         set_error("twa_adjoint: the reverse sweep is defined for the Heun integrator");
+        return TWA_EINVAL;
+    }
+    if (p->adjoint_objectives < 0 || p->adjoint_objectives > 3) {
+        set_error("twa_adjoint: adjoint_objectives is a mask of 1 (<S+S->) and 2 (g2), 0 = both");
         return TWA_EINVAL;
     }
     const int64_t burnin = p->burnin < 0 ? n_steps / 2 : p->burnin;

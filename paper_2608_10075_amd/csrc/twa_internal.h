@@ -96,7 +96,9 @@ struct StepConsts {
 // Type-erased description of one contraction launch (pointers are device
 // buffers of the geometry's precision; kinds: 0 primal, 1 response tangent,
 // 2 store (out = in + sign * A X), 3 adjoint of the corrector, 4 adjoint of
-// the predictor).
+// the predictor, 5 semi-implicit, KIND_PRIMAL_WITH_Q the predictor that also
+// stores the contribution of the second K half into Sout).
+constexpr int KIND_PRIMAL_WITH_Q = 0x100;
 struct GemmCall {
     int kind = 0, stage = 1, ncopy = 1;
     const void* A = nullptr;

@@ -71,6 +71,7 @@ struct GemmArgs {
     const S* Sin;
     S* Sout;
     S store_sign;
+    int kq;                 // snapshot kind: K stage at which the second K half starts
     // adjoint kinds (copy cp = objective)
     int64_t N, B;
     const S* Y2in;          // stage-2 contraction output of the primal step
@@ -86,7 +87,9 @@ struct GemmArgs {
     int src_on;             // the state produced by this backward step is observed
 };
 
-enum { KIND_PRIMAL = 0, KIND_TANGENT = 1, KIND_STORE = 2, KIND_ADJ2 = 3, KIND_ADJ1 = 4, KIND_SIB = 5 };
+enum { KIND_PRIMAL = 0, KIND_TANGENT = 1, KIND_STORE = 2, KIND_ADJ2 = 3, KIND_ADJ1 = 4, KIND_SIB = 5,
+       KIND_Q_SNAPSHOT = 0x100 };
+static_assert(KIND_PRIMAL_WITH_Q == (KIND_PRIMAL | KIND_Q_SNAPSHOT), "kind encoding");
 
 // Semi-implicit midpoint stage (the scheme the paper cites for its
 // spin-length-preserving integration): solve s' = s + ((s + s')/2) x b with
@@ -138,8 +141,14 @@ __device__ __forceinline__ void stg4(typename Prec<PREC>::G* p, const typename P
 // contraction over K on MFMA followed by the fused epilogue of the kind.
 template <int PREC, int MT, int NT, int KB, int WMW, int WNW, int NST, int STAGE, int KIND>
 __device__ __forceinline__ void stage_tile(const GemmArgs<PREC>& a, const int mt, const int nt, const int cp) {
-    constexpr bool TAN = KIND == KIND_TANGENT;
-    constexpr bool ADJ = KIND == KIND_ADJ2 || KIND == KIND_ADJ1;
+    // KIND_Q_SNAPSHOT on the predictor kind: also store the part of the
+    // contraction that comes from the second K half (the noise columns), by
+    // keeping the accumulator at the half-way K stage
+    constexpr int KD = KIND & ~KIND_Q_SNAPSHOT;
+    constexpr bool QSNAP = (KIND & KIND_Q_SNAPSHOT) != 0;
+    static_assert(!QSNAP || (KD == KIND_PRIMAL && STAGE == 1), "snapshot only on the predictor");
+    constexpr bool TAN = KD == KIND_TANGENT;
+    constexpr bool ADJ = KD == KIND_ADJ2 || KD == KIND_ADJ1;
     constexpr bool TCOPY = TAN || ADJ;     // per-copy collective sums of the copy operand
     typedef typename Prec<PREC>::G G;
     typedef typename Prec<PREC>::S S;
@@ -189,6 +198,7 @@ __device__ __forceinline__ void stage_tile(const GemmArgs<PREC>& a, const int mt
 
     // ---- main loop: acc[i][col] = sum_k A[m0+i][k] X[n0+col][k]
     AV acc[BI][BJ];
+    AV accW[QSNAP ? BI : 1][QSNAP ? BJ : 1];   // accumulator at K stage kq (snapshot kind)
 #pragma unroll
     for (int i = 0; i < BI; ++i)
 #pragma unroll
@@ -265,8 +275,8 @@ __device__ __forceinline__ void stage_tile(const GemmArgs<PREC>& a, const int mt
     // q in [g nmt / NG, (g+1) nmt / NG) in order, then the groups are added in
     // order (a fixed summation order: the result does not depend on timing).
     // Channels: 0, 1 primal x, y; 2, 3 copy x, y; 4 primal z.
-    if constexpr (KIND != KIND_STORE) {
-        constexpr int NCHAN = KIND == KIND_ADJ1 ? 5 : TCOPY ? 4 : 2;
+    if constexpr (KD != KIND_STORE) {
+        constexpr int NCHAN = KD == KIND_ADJ1 ? 5 : TCOPY ? 4 : 2;
         {
             const int kl = tid % NTRJ, gq = tid / NTRJ;
             const int64_t k = k0t + kl;
@@ -282,7 +292,7 @@ __device__ __forceinline__ void stage_tile(const GemmArgs<PREC>& a, const int mt
                     v[2] += tp[(0 * nmt + q) * Bp + k];
                     v[3] += tp[(1 * nmt + q) * Bp + k];
                 }
-                if constexpr (KIND == KIND_ADJ1) v[4] += pp[(2 * nmt + q) * Bp + k];
+                if constexpr (KD == KIND_ADJ1) v[4] += pp[(2 * nmt + q) * Bp + k];
             }
 #pragma unroll
             for (int c = 0; c < NCHAN; ++c) red[gq][kl][c] = v[c];
@@ -299,14 +309,14 @@ __device__ __forceinline__ void stage_tile(const GemmArgs<PREC>& a, const int mt
             const S sx = v[0], sy = v[1];
             sS[t][0] = sx;
             sS[t][1] = sy;
-            if constexpr (KIND == KIND_PRIMAL || KIND == KIND_SIB) {
+            if constexpr (KD == KIND_PRIMAL || KD == KIND_SIB) {
                 if (a.Sn) {
                     if constexpr (STAGE == 1) {
                         if (mt == 0) {
                             a.Sn[k] = sx;
                             a.Sn[Bp + k] = sy;
                         }
-                    } else if (a.dlt == nullptr || KIND == KIND_SIB) {
+                    } else if (a.dlt == nullptr || KD == KIND_SIB) {
                         // sums of the step's input state, for the predictor increment
                         sT[t][0] = a.Sn[k];
                         sT[t][1] = a.Sn[Bp + k];
@@ -319,7 +329,7 @@ __device__ __forceinline__ void stage_tile(const GemmArgs<PREC>& a, const int mt
                 sT[t][0] = v[2];
                 sT[t][1] = v[3];
             }
-            if constexpr (KIND == KIND_ADJ1) {
+            if constexpr (KD == KIND_ADJ1) {
                 // derivative of the observed moments (T2, T3, T4, Z, ZZ) of this
                 // trajectory's state with respect to any one spin component
                 const S sz = v[4];
@@ -361,6 +371,14 @@ __device__ __forceinline__ void stage_tile(const GemmArgs<PREC>& a, const int mt
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
                 if (kt + NST - 1 < nk) TWA_DMA(kt + NST - 1, TWA_BUF((u + NST - 1) % NST));
                 __builtin_amdgcn_sched_barrier(0);
+                if constexpr (QSNAP) {
+                    if (kt == a.kq) {
+#pragma unroll
+                        for (int i = 0; i < BI; ++i)
+#pragma unroll
+                            for (int j = 0; j < BJ; ++j) accW[i][j] = acc[i][j];
+                    }
+                }
                 TWA_COMPUTE(TWA_BUF(u));
             }
         }
@@ -386,12 +404,12 @@ __device__ __forceinline__ void stage_tile(const GemmArgs<PREC>& a, const int mt
             const int64_t i0 = m0 + wm0 + 16 * bi + 4 * (lane >> 4);
             const int64_t off = k * P + i0;
             S x[4], y[4], z[4];
-            if constexpr (KIND != KIND_STORE) {
+            if constexpr (KD != KIND_STORE) {
                 ld4(a.s_cur + off, x);
                 ld4(a.s_cur + SP + off, y);
                 ld4(a.s_cur + 2 * SP + off, z);
             }
-            if constexpr (KIND == KIND_PRIMAL && STAGE == 1) {
+            if constexpr (KD == KIND_PRIMAL && STAGE == 1) {
                 S dx[4], dy[4], dz[4], yx[4], yy[4];
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
@@ -415,7 +433,17 @@ __device__ __forceinline__ void stage_tile(const GemmArgs<PREC>& a, const int mt
                 st4(a.Y + SP + off, yy);
                 stg4<PREC>(a.Dop + opcol(k, 0) * P + i0, dx);
                 stg4<PREC>(a.Dop + opcol(k, 1) * P + i0, dy);
-            } else if constexpr (KIND == KIND_SIB && STAGE == 1) {
+                if constexpr (QSNAP) {
+                    S qx[4], qy[4];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        qx[r] = acc[bi][2 * p][r] - accW[bi][2 * p][r];
+                        qy[r] = acc[bi][2 * p + 1][r] - accW[bi][2 * p + 1][r];
+                    }
+                    st4(a.Sout + off, qx);
+                    st4(a.Sout + SP + off, qy);
+                }
+            } else if constexpr (KD == KIND_SIB && STAGE == 1) {
                 // predictor: the midpoint rule with the field at s_n
                 S dx[4], dy[4], yx[4], yy[4];
 #pragma unroll
@@ -435,7 +463,7 @@ __device__ __forceinline__ void stage_tile(const GemmArgs<PREC>& a, const int mt
                 st4(a.Y + SP + off, yy);
                 stg4<PREC>(a.Dop + opcol(k, 0) * P + i0, dx);
                 stg4<PREC>(a.Dop + opcol(k, 1) * P + i0, dy);
-            } else if constexpr (KIND == KIND_SIB && STAGE == 2) {
+            } else if constexpr (KD == KIND_SIB && STAGE == 2) {
                 // corrector: the midpoint rule from s_n with the field at the
                 // midpoint m = s_n + D/2: contraction Y1 + A_left D / 2, sums (S_n + S~)/2
                 S yx[4], yy[4], nx[4], ny[4], nz[4];
@@ -457,7 +485,7 @@ __device__ __forceinline__ void stage_tile(const GemmArgs<PREC>& a, const int mt
                 st4(a.s_next + 2 * SP + off, nz);
                 stg4<PREC>(a.Xnext + opcol(k, 0) * a.ldxn + i0, nx);
                 stg4<PREC>(a.Xnext + opcol(k, 1) * a.ldxn + i0, ny);
-            } else if constexpr (KIND == KIND_PRIMAL && STAGE == 2) {
+            } else if constexpr (KD == KIND_PRIMAL && STAGE == 2) {
                 S dx[4], dy[4], dz[4], yx[4], yy[4], nx[4], ny[4], nz[4];
                 ld4(a.Y + off, yx);
                 ld4(a.Y + SP + off, yy);
@@ -503,7 +531,7 @@ __device__ __forceinline__ void stage_tile(const GemmArgs<PREC>& a, const int mt
                 }
                 stg4<PREC>(a.Xnext + opcol(k, 0) * a.ldxn + i0, nx);
                 stg4<PREC>(a.Xnext + opcol(k, 1) * a.ldxn + i0, ny);
-            } else if constexpr (KIND == KIND_TANGENT && STAGE == 1) {
+            } else if constexpr (KD == KIND_TANGENT && STAGE == 1) {
                 const S tSx = sT[kl][0], tSy = sT[kl][1];
                 const S* tc = a.t_cur + cp * a.t_state_copy;
                 S u[4], v[4], w[4], yx[4], yy[4], ex[4], ey[4], ez[4], ax4[4], ay4[4];
@@ -536,7 +564,7 @@ __device__ __forceinline__ void stage_tile(const GemmArgs<PREC>& a, const int mt
                 G* tdo = a.tDop + cp * a.t_op_copy;
                 stg4<PREC>(tdo + opcol(k, 0) * P + i0, ex);
                 stg4<PREC>(tdo + opcol(k, 1) * P + i0, ey);
-            } else if constexpr (KIND == KIND_STORE) {
+            } else if constexpr (KD == KIND_STORE) {
                 S ox[4], oy[4];
                 if (a.Sin) {
                     ld4(a.Sin + off, ox);
@@ -552,7 +580,7 @@ __device__ __forceinline__ void stage_tile(const GemmArgs<PREC>& a, const int mt
                 }
                 st4(a.Sout + off, ox);
                 st4(a.Sout + SP + off, oy);
-            } else if constexpr (KIND == KIND_ADJ2) {
+            } else if constexpr (KD == KIND_ADJ2) {
                 // reverse of the corrector: lam' -> (mu1, R = lam' + cotangent of s~, nu1)
                 const int64_t co = cp * a.t_state_copy;
                 S lx[4], ly[4], lz[4], dx[4], dy[4], dz[4], y2x[4], y2y[4], qx[4], qy[4], ax_[4], ay_[4];
@@ -602,7 +630,7 @@ __device__ __forceinline__ void stage_tile(const GemmArgs<PREC>& a, const int mt
                 G* no = a.Xnext + cp * a.t_op_copy;
                 stg4<PREC>(no + opcol(k, 0) * a.ldxn + i0, n1x);
                 stg4<PREC>(no + opcol(k, 1) * a.ldxn + i0, n1y);
-            } else if constexpr (KIND == KIND_ADJ1) {
+            } else if constexpr (KD == KIND_ADJ1) {
                 // reverse of the predictor: (mu1, R) -> lam of the step's input state
                 const int64_t co = cp * a.t_state_copy;
                 S mx[4], my[4], mz[4], rx[4], ry[4], rz[4], y1x[4], y1y[4], qx[4], qy[4], ax_[4], ay_[4];
@@ -699,15 +727,15 @@ __device__ __forceinline__ void stage_tile(const GemmArgs<PREC>& a, const int mt
             red[wm][kl][3] = ps3;
         }
     }
-    if constexpr (KIND != KIND_STORE) {
+    if constexpr (KD != KIND_STORE) {
         __syncthreads();
-        if constexpr (KIND == KIND_PRIMAL || KIND == KIND_SIB || KIND == KIND_TANGENT || KIND == KIND_ADJ2) {
+        if constexpr (KD == KIND_PRIMAL || KD == KIND_SIB || KD == KIND_TANGENT || KD == KIND_ADJ2) {
             // ADJ2: channels 0, 1 are the spin sums of nu1 (its z channel is zero)
             S* po = a.part_out + (TCOPY ? cp * a.t_part_copy : 0);
             for (int t = tid; t < 3 * NTRJ; t += NTHR) {
                 const int c = t / NTRJ, kl = t % NTRJ;
                 S sum = 0;
-                if (KIND != KIND_ADJ2 || c < 2) {
+                if (KD != KIND_ADJ2 || c < 2) {
 #pragma unroll
                     for (int q = 0; q < WMW; ++q) sum += red[q][kl][c];
                 }
@@ -820,6 +848,8 @@ static int dispatch_kind(const GemmArgs<PREC>& a, int stage, int kind, int64_t P
             case KIND_SIB: return launch_kernel<PREC, CFG, 1, KIND_SIB>(a, P, C2, ncopy, st);
             case KIND_TANGENT: return launch_kernel<PREC, CFG, 1, KIND_TANGENT>(a, P, C2, ncopy, st);
             case KIND_STORE: return launch_kernel<PREC, CFG, 1, KIND_STORE>(a, P, C2, ncopy, st);
+            case KIND_PRIMAL | KIND_Q_SNAPSHOT:
+                return launch_kernel<PREC, CFG, 1, KIND_PRIMAL | KIND_Q_SNAPSHOT>(a, P, C2, ncopy, st);
             case KIND_ADJ1: return launch_kernel<PREC, CFG, 1, KIND_ADJ1>(a, P, C2, ncopy, st);
         }
     } else {
@@ -989,6 +1019,7 @@ static int launch_call_p(const Geometry& g, const GemmCall& c, hipStream_t st) {
     a.Sin = static_cast<const S*>(c.Sin);
     a.Sout = static_cast<S*>(c.Sout);
     a.store_sign = (S)c.store_sign;
+    a.kq = (int)(g.P / g.kt);
     a.Y2in = static_cast<const S*>(c.Y2in);
     a.Qin = static_cast<const S*>(c.Qin);
     a.YA = static_cast<const S*>(c.YA);

@@ -96,3 +96,19 @@ def test_adjoint_rejects_bad_arguments(twa):
         twa.adjoint(p, 8, 1e-3, 10, precision="bf16")
     with pytest.raises(twa.TWAError):
         twa.adjoint(p, 8, 1e-3, 10, ckpt_every=0)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_single_objective_sweep_equals_its_copy_of_the_joint_sweep(twa, prec):
+    """Each objective is an independent copy of the reverse sweep: asking for one
+    gives exactly that copy's gradients (the other entries are NaN)."""
+    N, B, w, alpha, dt, T = 40, 48, 1.5, 0.8, 1e-3, 160
+    p = twa.build_pump(N, w, alpha)
+    _, both = twa.adjoint(p, B, dt, T, seed=3, ckpt_every=64, precision=prec)
+    for sel, keys in ((("g2",), ("d_g2_dw", "d_g2_dalpha")), (("SpSm",), ("d_SpSm_dw", "d_SpSm_dalpha"))):
+        _, one = twa.adjoint(p, B, dt, T, seed=3, ckpt_every=64, precision=prec, objectives=sel)
+        for k in KEYS:
+            if k in keys:
+                assert one[k] == both[k], (sel, k)
+            else:
+                assert np.isnan(one[k])
