@@ -60,6 +60,9 @@ extern "C" {
 #define TWA_PREC_BF16   2   /* FP32 state, BF16 MFMA inputs, FP32 accumulation */
 #define TWA_PREC_FP16   3   /* FP32 state, FP16 MFMA inputs, FP32 accumulation */
 
+/* tile_config reported when the fused small-N kernel integrated the run */
+#define TWA_TILE_FUSED  99
+
 /* ---- integrators ------------------------------------------------------ */
 #define TWA_INT_HEUN    0   /* stochastic Heun, Stratonovich reading of Eq. (S1) */
 #define TWA_INT_SIB     1   /* semi-implicit midpoint scheme (the spin-length-preserving
@@ -130,7 +133,8 @@ typedef struct twa_params {
     int64_t n_lags;          /* two-time lags L (0 = no two-time correlation)      */
     int64_t lag_stride;      /* steps per lag; <= 0 = max(1, (n_steps-burnin)/L)   */
     int32_t point;           /* Philox point index (counter word 3, bits 8..31)    */
-    int32_t tile_config;     /* < 0: automatic (autotuner cache / heuristic)       */
+    int32_t tile_config;     /* < 0: automatic (heuristic; N <= 64 in FP64/FP32    */
+                             /* without two-time runs the fused small-N kernel)    */
     void* stream;            /* hipStream_t, NULL = null stream                    */
     const double* init_state;/* host, optional [3][n_traj][N] (x, y, z planes):    */
                              /* replaces the discrete sampling when non-NULL       */
@@ -166,7 +170,8 @@ typedef struct twa_observables {
     double max_norm_dev;     /* max over spins of | |s|^2(end) - |s|^2(start) |    */
     double step_criterion;   /* max(Gamma N, lam_max) dt; the paper asks < 0.05    */
     int32_t nan_flag;        /* 1 if a NaN/Inf was seen                            */
-    int32_t tile_config;     /* tile configuration used                            */
+    int32_t tile_config;     /* tile configuration used (TWA_TILE_FUSED: the fused */
+                             /* small-N kernel, every step in one launch)          */
     double kernel_ms;        /* device time of the step loop (HIP events)          */
     double stage1_ms;        /* timing = 1: summed device time of the predictor    */
     int64_t stage1_launches; /* contraction launches (HIP events around each) and  */

@@ -160,6 +160,11 @@ int launch_philox(const uint32_t* ctr, int64_t n, uint32_t k0, uint32_t k1, uint
 int launch_noise_debug(uint64_t seed, int64_t step, int32_t point, int64_t B, int64_t N, int fp64,
                        double* zeta, double* g, hipStream_t st);
 
+// fused small-N path (twa_small.hip): every step in one launch
+bool small_path_applies(int precision, int64_t N, int64_t n_lags);
+int launch_small_run(const Geometry& g, const EnsembleBuffers& b, const StepConsts& c, const twa_pump* pump,
+                     double dt, int64_t n_steps, int out_cur, hipStream_t st);
+
 // pump (twa_pump.hip): the Eq. (2) pump of a handle rescaled to amplitude w
 int pump_scaled(const twa_pump* base, double w, twa_pump** out);
 }  // namespace twa

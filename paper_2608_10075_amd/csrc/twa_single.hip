@@ -107,6 +107,7 @@ int run_single(const twa_params* p, int64_t n_traj, double dt, int64_t n_steps, 
     }
     Geometry g = make_geometry(p->precision, cfg, N, B);
     g.integrator = p->integrator;
+    const bool fused = p->tile_config < 0 && small_path_applies(p->precision, N, L);
     const int J = (int)std::min<int64_t>(32, B);
     const bool tangents = L > 0;
 
@@ -183,6 +184,12 @@ int run_single(const twa_params* p, int64_t n_traj, double dt, int64_t n_steps, 
     TWA_HTRY(hipEventCreate(&e0));
     TWA_HTRY(hipEventCreate(&e1));
     TWA_HTRY(hipEventRecord(e0, st));
+    if (fused) {
+        // one launch integrates every step (short chains are bound by per-step latency)
+        cur = (int)(n_steps & 1);
+        TWA_TRY(launch_small_run(g, b, c, pump, dt, n_steps, cur, st));
+        n = n_steps;
+    }
     while (n < n_steps) {
         const StepKind k = plan.kind(n);
         int64_t run = 1;
@@ -263,7 +270,7 @@ int run_single(const twa_params* p, int64_t n_traj, double dt, int64_t n_steps, 
         out->max_norm_dev = mx;
         out->step_criterion = std::max(p->gamma * (double)N, pump->lam_max) * dt;
         out->nan_flag = nan ? 1 : 0;
-        out->tile_config = cfg;
+        out->tile_config = fused ? TWA_TILE_FUSED : cfg;
         out->kernel_ms = loop_ms;
         if (tm) {
             tm->s1.harvest(st);
