@@ -32,7 +32,15 @@ GPU-accelerated Truncated Wigner dynamics"):
                      observables with respect to w and alpha by forward-mode
                      tangent propagation, and the Sylvester solve for dF/dalpha.
 * ``lindblad``    -- brute-force density-matrix Lindbladian of Eq. (1) for tiny
-                     N, used only to pin the oracle's equations of motion.
+                     N (optionally with a correlated-decay matrix in place of
+                     the collective term), used only to pin the oracle's
+                     equations of motion.
+* ``decay``       -- correlated decay (the general-matrix extension named in
+                     the Perspectives): the step's matrices W - G and
+                     sqrt(W + G), and the intensity and four-point function of
+                     correlated emission (SM Sec. S1 step 6) with jackknife.
+* ``protocol``    -- the paper's time-step criterion, preparation time and
+                     window, and the threshold / g2-minimum searches.
 * ``closed_forms``-- the alpha=0 closed forms (noiseless superradiant decay and
                      the stationary law of the collective spin) used as pins.
 

@@ -29,12 +29,25 @@ def operators(n):
     return sig_p, sig_m, sig_z
 
 
-def lindblad_rhs(rho, W, gamma, ops):
+def lindblad_rhs(rho, W, gamma, ops, decay=None):
+    """Right-hand side of Eq. (1).  With ``decay`` (an N x N matrix G) the
+    collective term is replaced by correlated decay,
+    sum_ab G_ab/2 (2 sigma-_b rho sigma+_a - {sigma+_a sigma-_b, rho})
+    (G = Gamma * ones gives the collective term back)."""
     sig_p, sig_m, _ = ops
-    Sp = sum(sig_p)
-    Sm = sum(sig_m)
-    out = 0.5 * gamma * (2 * Sm @ rho @ Sp - Sp @ Sm @ rho - rho @ Sp @ Sm)
     n = len(sig_p)
+    if decay is None:
+        Sp = sum(sig_p)
+        Sm = sum(sig_m)
+        out = 0.5 * gamma * (2 * Sm @ rho @ Sp - Sp @ Sm @ rho - rho @ Sp @ Sm)
+    else:
+        out = np.zeros_like(rho)
+        for a in range(n):
+            for b in range(n):
+                if decay[a, b] == 0:
+                    continue
+                A = sig_p[a] @ sig_m[b]
+                out += 0.5 * decay[a, b] * (2 * sig_m[b] @ rho @ sig_p[a] - A @ rho - rho @ A)
     for i in range(n):
         for j in range(n):
             if W[i, j] == 0:

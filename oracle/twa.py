@@ -13,7 +13,9 @@ Follows SM Sec. S1 of the paper step by step:
    ``oracle.observables``; equal-time observables are also averaged over the
    window (closing remark of SM Sec. S1);
 and the two-time correlation (Eq. (S3) and the three-copy response that
-follows it).
+follows it).  With ``RunConfig.decay`` the collective decay is replaced by a
+correlated-decay matrix (``oracle.decay``) and the window also accumulates the
+nine per-trajectory quantities of the correlated-emission estimator.
 
 Readings where the paper is silent (listed with the others in the design
 notes of the repository):
@@ -36,11 +38,12 @@ notes of the repository):
 """
 from __future__ import annotations
 
-from dataclasses import dataclass, field
+from dataclasses import dataclass, field, replace
 from typing import Optional
 
 import numpy as np
 
+from . import decay as odecay
 from . import philox
 from .pump import Pump, build_pump
 
@@ -67,6 +70,8 @@ class RunConfig:
     traj: Optional[np.ndarray] = None      # trajectory indices (n_traj,) of the noise counters;
                                            # None: 0 .. n_traj-1 (trajectories are independent,
                                            # so any subset of an ensemble can be integrated alone)
+    decay: Optional[np.ndarray] = None     # (N, N) symmetric PSD correlated-decay matrix G; replaces
+                                           # the collective decay (gamma unused), see oracle.decay
 
     def resolved_burnin(self) -> int:
         return self.n_steps // 2 if self.burnin is None else int(self.burnin)
@@ -233,6 +238,13 @@ def run(cfg: RunConfig, pump: Optional[Pump] = None) -> RunResult:
     """Integrate all trajectories and accumulate the observables."""
     if pump is None:
         pump = build_pump(cfg.n_spin, cfg.w, cfg.alpha)
+    G = None
+    if cfg.decay is not None:
+        if cfg.n_lags > 0:
+            raise NotImplementedError("two-time correlation of correlated emission is not defined here")
+        G = np.asarray(cfg.decay, dtype=np.float64)
+        pump = odecay.model_pump(pump.W, G)
+        cfg = replace(cfg, gamma=0.0)    # the matrix replaces the collective terms
     W = pump.W
     B, T = cfg.n_traj, cfg.n_steps
     burn = cfg.resolved_burnin()
@@ -243,6 +255,7 @@ def run(cfg: RunConfig, pump: Optional[Pump] = None) -> RunResult:
     norm0 = state[0] ** 2 + state[1] ** 2 + state[2] ** 2
 
     acc = np.zeros((B, 5))
+    gen_acc = np.zeros((B, 9)) if G is not None else None
     n_samples = 0
     L = int(cfg.n_lags)
     stride = cfg.resolved_stride()
@@ -303,6 +316,8 @@ def run(cfg: RunConfig, pump: Optional[Pump] = None) -> RunResult:
         k = n + 1
         if k > burn:
             acc += moments(state)
+            if G is not None:
+                gen_acc += odecay.general_quantities(state, G)
             n_samples += 1
         if L > 0:
             if k == burn:
@@ -312,9 +327,12 @@ def run(cfg: RunConfig, pump: Optional[Pump] = None) -> RunResult:
                 lag_accumulate((k - burn) // stride, state)
     traj = acc / max(n_samples, 1)
     norm1 = state[0] ** 2 + state[1] ** 2 + state[2] ** 2
-    return RunResult(traj_moments=traj, n_samples=n_samples, final_state=state,
-                     corr_blocks=corr_blocks, chi_blocks=chi_blocks, n_lags=L,
-                     lag_stride=stride, max_norm_dev=float(np.max(np.abs(norm1 - norm0))))
+    res = RunResult(traj_moments=traj, n_samples=n_samples, final_state=state,
+                    corr_blocks=corr_blocks, chi_blocks=chi_blocks, n_lags=L,
+                    lag_stride=stride, max_norm_dev=float(np.max(np.abs(norm1 - norm0))))
+    if G is not None:
+        res.extra["traj_gen"] = gen_acc / max(n_samples, 1)
+    return res
 
 
 def run_steps(state, pump: Pump, cfg: RunConfig, first_step: int, n_steps: int):
