@@ -103,6 +103,25 @@ TWA_API int twa_build_pump(int64_t N, double w, double alpha, twa_pump** out);
  */
 TWA_API int twa_build_pump_dense(int64_t N, const double* W_host, twa_pump** out);
 
+/*
+ * twa_build_model_dense -- a model handle for correlated decay: the pump W
+ * and a correlated-decay matrix G (both host, row-major FP64, N x N,
+ * symmetric; G must be PSD and is G_ab of SM Sec. S1 step 6), the general
+ * decay matrix the paper's Perspectives name.  With such a handle twa_run
+ * integrates Eq. (S1) with the collective terms (1/2) Gamma S^a and xi^a
+ * replaced by (1/2) sum_j G_ij s^a_j and a noise of covariance G_ij (params
+ * gamma is ignored), and reports the correlated-emission intensity and g2
+ * (twa_observables I_gen, g2_gen).  The decay and pump noises are drawn as
+ * one Gaussian of covariance (W + G) dt (equal in law to two independent
+ * draws): the handle stores the drift matrix W - G (twa_pump_copy_matrix
+ * which = 0), the PSD square root of W + G (which = 1) and G (which = 2);
+ * twa_pump_info reports the eigenvalue range of W + G.  Not accepted by
+ * twa_adjoint, and twa_run rejects it with n_lags > 0.
+ * Errors: TWA_EINVAL (bad sizes, non-finite or non-symmetric input),
+ *         TWA_ENOTPSD (G or W + G not PSD), TWA_ENOMEM, TWA_EHIP.
+ */
+TWA_API int twa_build_model_dense(int64_t N, const double* W_host, const double* G_host, twa_pump** out);
+
 /* Releases a handle from twa_build_pump*; NULL is ignored. */
 TWA_API void twa_pump_free(twa_pump* p);
 
@@ -115,8 +134,9 @@ TWA_API void twa_pump_free(twa_pump* p);
 TWA_API int twa_pump_info(const twa_pump* p, int64_t* N, double* lam_min, double* lam_max);
 
 /*
- * twa_pump_copy_matrix -- copies W (which = 0) or F (which = 1) into a host
- * row-major N x N FP64 buffer.  Errors: TWA_EINVAL, TWA_EHIP.
+ * twa_pump_copy_matrix -- copies W (which = 0), F (which = 1) or, for a model
+ * handle, the decay matrix G (which = 2) into a host row-major N x N FP64
+ * buffer.  Errors: TWA_EINVAL, TWA_EHIP.
  */
 TWA_API int twa_pump_copy_matrix(const twa_pump* p, int which, double* out_host);
 
@@ -125,7 +145,8 @@ TWA_API int twa_pump_copy_matrix(const twa_pump* p, int which, double* out_host)
  * ====================================================================== */
 typedef struct twa_params {
     const twa_pump* pump;    /* required                                          */
-    double gamma;            /* collective decay rate Gamma (> 0)                  */
+    double gamma;            /* collective decay rate Gamma (> 0); ignored with a  */
+                             /* model handle (twa_build_model_dense)              */
     double s0z;              /* initial s^z of every spin: +1 excited, -1 ground   */
     int64_t burnin;          /* steps before the averaging window; < 0 = n_steps/2 */
     int32_t integrator;      /* TWA_INT_HEUN or TWA_INT_SIB                        */
@@ -187,6 +208,11 @@ typedef struct twa_observables {
     double adjoint_fwd_ms;   /* twa_adjoint: device time of the checkpointed       */
     double adjoint_bwd_ms;   /* forward run and of the reverse sweep (recompute    */
                              /* included); kernel_ms is their sum                  */
+    /* correlated decay (model handles; NaN otherwise), SM Sec. S1 step 6:
+       I_gen = <sum_ab G_ab s+_a s-_b> = <E2>_TWA + (1/2) sum_a G_aa <s^z_a>_TWA;
+       g2_gen = sum_abcd G_ad G_bc <s+_a s+_b s-_c s-_d> / I_gen^2 from the
+       printed four-point expression; jackknife errors as above              */
+    double I_gen, g2_gen, I_gen_se, g2_gen_se;
 } twa_observables;
 
 /* Optional host output buffers of twa_run (any may be NULL). */
@@ -199,6 +225,11 @@ typedef struct twa_outputs {
                                 T2, T3, T4, Z, ZZ                                 */
     double* final_state;     /* [3][n_traj][N] x, y, z planes at the last step    */
     int32_t* n_blocks;       /* receives J                                        */
+    double* traj_gen;        /* model handles: [n_traj][9] window averages of E2,
+                                E2^2, E2 D, Q3, R, D^2, U, V, D with
+                                E2 = sum_ab G_ab s+_a s-_b, D = sum_a G_aa s^z_a,
+                                Q3 = sum_b s^z_b |(G s+)_b|^2, R = sum_a G_aa^2 s^z_a,
+                                U = s^z . (G o G) s^z, V = Re sum_ab G_aa G_ab s+_a s-_b */
 } twa_outputs;
 
 /*
@@ -217,9 +248,14 @@ typedef struct twa_outputs {
  *   lag l samples the state after burnin + l * stride steps.
  *   out   host, required: scalar results.
  *   outs  host, optional: per-block / per-trajectory arrays.
+ *   Model handle (twa_build_model_dense): correlated decay in place of the
+ *   collective terms; every observed state also passes through G [s^x, s^y]
+ *   and (G o G) s^z contractions in the run's contraction precision, and the
+ *   correlated-emission intensity and g2 are reported (I_gen, g2_gen).
  * Errors: TWA_EINVAL (NULL pump/out, n_traj < 1, n_steps < 0, dt <= 0,
- *         burnin > n_steps, gamma <= 0, unknown precision, lags that do not
- *         fit: (n_lags - 1) * stride > n_steps - burnin), TWA_ENOMEM,
+ *         burnin > n_steps, gamma <= 0 without a model handle, unknown
+ *         precision, lags that do not fit: (n_lags - 1) * stride >
+ *         n_steps - burnin, n_lags > 0 with a model handle), TWA_ENOMEM,
  *         TWA_EHIP, TWA_EUNSTABLE.
  * Deterministic: identical inputs give bitwise identical outputs.
  */

@@ -65,17 +65,21 @@ def model_pump(W: np.ndarray, G: np.ndarray) -> Pump:
 
 def general_quantities(state, G: np.ndarray) -> np.ndarray:
     """The nine per-trajectory quantities of the correlated-emission estimator,
-    (n_traj, 9), from the state (x, y, z) each (n_traj, N)."""
+    (n_traj, 9), from the state (x, y, z) each (n_traj, N).  The index sums
+    are grouped into matrix-vector products: (G s-)_a = sum_b G_ab s-_b and
+    (G^T s+)_b = sum_a G_ab s+_a."""
     x, y, z = state
     sp = 0.5 * (x + 1j * y)
     sm = 0.5 * (x - 1j * y)
     dg = np.diag(G)
-    E2 = np.einsum("ab,ka,kb->k", G, sp, sm).real
-    D = np.einsum("a,ka->k", dg, z)
-    Q3 = np.einsum("ab,bc,ka,kc,kb->k", G, G, sp, sm, z).real
-    R = np.einsum("a,ka->k", dg * dg, z)
-    U = np.einsum("ab,ba,ka,kb->k", G, G, z, z)
-    V = np.einsum("a,ab,ka,kb->k", dg, G, sp, sm).real
+    Gsm = sm @ G.T               # (G s-)_a
+    GTsp = sp @ G                # (G^T s+)_b
+    E2 = np.sum(sp * Gsm, axis=1).real
+    D = z @ dg
+    Q3 = np.sum(z * GTsp * Gsm, axis=1).real
+    R = z @ (dg * dg)
+    U = np.sum(z * (z @ (G * G.T).T), axis=1)
+    V = np.sum(dg * sp * Gsm, axis=1).real
     return np.stack([E2, E2 * E2, E2 * D, Q3, R, D * D, U, V, D], axis=1)
 
 

@@ -52,13 +52,15 @@ class _Obs(C.Structure):
                  ("tile_config", C.c_int32), ("kernel_ms", C.c_double), ("stage1_ms", C.c_double),
                  ("stage1_launches", C.c_int64), ("stage2_ms", C.c_double), ("stage2_launches", C.c_int64),
                  ("gemm_flops", C.c_double), ("linewidth", C.c_double),
-                 ("linewidth_sym", C.c_double), ("adjoint_fwd_ms", C.c_double), ("adjoint_bwd_ms", C.c_double)])
+                 ("linewidth_sym", C.c_double), ("adjoint_fwd_ms", C.c_double), ("adjoint_bwd_ms", C.c_double),
+                 ("I_gen", C.c_double), ("g2_gen", C.c_double), ("I_gen_se", C.c_double),
+                 ("g2_gen_se", C.c_double)])
 
 
 class _Outs(C.Structure):
     _fields_ = [("corr_blocks", C.POINTER(C.c_double)), ("chi_blocks", C.POINTER(C.c_double)),
                 ("traj_moments", C.POINTER(C.c_double)), ("final_state", C.POINTER(C.c_double)),
-                ("n_blocks", C.POINTER(C.c_int32))]
+                ("n_blocks", C.POINTER(C.c_int32)), ("traj_gen", C.POINTER(C.c_double))]
 
 
 class _Point(C.Structure):
@@ -92,6 +94,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.twa_version.restype = C.c_char_p
     lib.twa_build_pump.argtypes = [C.c_int64, C.c_double, C.c_double, C.POINTER(P)]
     lib.twa_build_pump_dense.argtypes = [C.c_int64, C.POINTER(C.c_double), C.POINTER(P)]
+    lib.twa_build_model_dense.argtypes = [C.c_int64, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(P)]
     lib.twa_pump_free.argtypes = [P]
     lib.twa_pump_free.restype = None
     lib.twa_pump_info.argtypes = [P, C.POINTER(C.c_int64), C.POINTER(C.c_double), C.POINTER(C.c_double)]
@@ -116,7 +119,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.twa_g2_min.argtypes = [C.c_int64, C.c_double, C.POINTER(_Params), C.c_int64, C.c_uint64, C.c_int32,
                                C.c_double, C.c_double, C.c_double, C.c_int32, C.POINTER(C.c_double),
                                C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double)]
-    for name in ("twa_build_pump", "twa_build_pump_dense", "twa_pump_info", "twa_pump_copy_matrix", "twa_run",
+    for name in ("twa_build_pump", "twa_build_pump_dense", "twa_build_model_dense", "twa_pump_info", "twa_pump_copy_matrix", "twa_run",
                  "twa_run_batch", "twa_adjoint", "twa_philox", "twa_noise", "twa_protocol", "twa_find_threshold",
                  "twa_g2_min"):
         getattr(lib, name).restype = C.c_int
@@ -149,11 +152,20 @@ def _stream_ptr(stream=None):
 
 class Pump:
     """Eq. (2) pump matrix, its channel decomposition and PSD noise factor
-    (library-owned device memory, released on ``close``/garbage collection)."""
+    (library-owned device memory, released on ``close``/garbage collection).
+    With ``decay`` (and ``dense``): a model handle for correlated decay."""
 
-    def __init__(self, N: int, w: float = None, alpha: float = None, dense: Optional[np.ndarray] = None):
+    def __init__(self, N: int, w: float = None, alpha: float = None, dense: Optional[np.ndarray] = None,
+                 decay: Optional[np.ndarray] = None):
         h = C.c_void_p()
-        if dense is not None:
+        self.has_decay = decay is not None
+        if decay is not None:
+            W = np.ascontiguousarray(dense, dtype=np.float64)
+            G = np.ascontiguousarray(decay, dtype=np.float64)
+            assert W.shape == (N, N) and G.shape == (N, N)
+            _check(_lib.twa_build_model_dense(int(N), W.ctypes.data_as(C.POINTER(C.c_double)),
+                                              G.ctypes.data_as(C.POINTER(C.c_double)), C.byref(h)))
+        elif dense is not None:
             W = np.ascontiguousarray(dense, dtype=np.float64)
             _check(_lib.twa_build_pump_dense(int(N), W.ctypes.data_as(C.POINTER(C.c_double)), C.byref(h)))
         else:
@@ -171,8 +183,10 @@ class Pump:
         return self._h
 
     def matrix(self, which: str = "W") -> np.ndarray:
+        """W (for a model handle: the drift matrix W - G), F (the noise factor)
+        or G (model handles: the decay matrix)."""
         out = np.empty((self.N, self.N))
-        _check(_lib.twa_pump_copy_matrix(self._h, 0 if which == "W" else 1,
+        _check(_lib.twa_pump_copy_matrix(self._h, {"W": 0, "F": 1, "G": 2}[which],
                                          out.ctypes.data_as(C.POINTER(C.c_double))))
         return out
 
@@ -192,6 +206,12 @@ def build_pump(N: int, w: float, alpha: float) -> Pump:
     return Pump(N, w, alpha)
 
 
+def build_model(W: np.ndarray, decay: np.ndarray) -> Pump:
+    """twa_build_model_dense: pump matrix W and correlated-decay matrix G."""
+    W = np.asarray(W, dtype=np.float64)
+    return Pump(W.shape[0], dense=W, decay=decay)
+
+
 @dataclass
 class RunResult:
     obs: dict
@@ -201,6 +221,7 @@ class RunResult:
     chi_blocks: Optional[np.ndarray] = None
     n_blocks: int = 0
     status: int = 0
+    traj_gen: Optional[np.ndarray] = None
 
 
 def _obs_dict(o: _Obs) -> dict:
@@ -240,6 +261,9 @@ def run(pump: Pump, n_traj: int, dt: float, n_steps: int, seed: int = 0, *, gamm
     if want_traj:
         res.traj_moments = np.zeros((n_traj, 5))
         outs.traj_moments = res.traj_moments.ctypes.data_as(C.POINTER(C.c_double))
+        if getattr(pump, "has_decay", False):
+            res.traj_gen = np.zeros((n_traj, 9))
+            outs.traj_gen = res.traj_gen.ctypes.data_as(C.POINTER(C.c_double))
     if want_final_state:
         res.final_state = np.zeros((3, n_traj, pump.N))
         outs.final_state = res.final_state.ctypes.data_as(C.POINTER(C.c_double))

@@ -426,6 +426,7 @@ int adjoint_impl(const twa_params* p, int64_t n_traj, double dt, int64_t n_steps
                     ns > 0 ? (hmom[(size_t)(2 * q) * g.Bp + k] - hmom[(size_t)(2 * q + 1) * g.Bp + k]) / (double)ns
                            : NAN;
         std::memset(out, 0, sizeof(*out));
+        out->I_gen = out->g2_gen = out->I_gen_se = out->g2_gen_se = NAN;
         finalize_moments(traj, B, out);
         out->n_samples = ns;
         out->step_criterion = std::max(p->gamma * (double)N, pump->lam_max) * dt;

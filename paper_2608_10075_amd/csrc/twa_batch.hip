@@ -430,6 +430,7 @@ int run_batch(const twa_point* pts, int np, const twa_batch_opts* o, twa_observa
         out.kernel_ms = loop_ms;   // the whole scan's step loop
         out.gemm_flops = 12.0 * (double)g.N * (double)g.N * (double)g.B * (double)o->n_steps;
         out.linewidth = NAN;
+        out.I_gen = out.g2_gen = out.I_gen_se = out.g2_gen_se = NAN;
         out.linewidth_sym = NAN;
         if (nan) rc = TWA_EUNSTABLE;
     }

@@ -79,6 +79,14 @@ struct EnsembleBuffers {
     void* tpart[2] = {nullptr, nullptr};// ST [2][3][nmt][Bp]
     void* sm0 = nullptr;        // ST [2][Bp]
     double* lag = nullptr;      // [L][J][6]
+    // correlated decay (model handles)
+    void* AG = nullptr;         // GT [P][P] G
+    void* AGG = nullptr;        // GT [P][P] G o G (elementwise square)
+    void* Zop = nullptr;        // GT [Bp][P] packed s^z operand
+    void* GX = nullptr;         // ST [2][Bp][P] G s^x, G s^y
+    void* UZ = nullptr;         // ST [Bp][P] (G o G) s^z
+    void* dg = nullptr;         // ST [P] diagonal of G
+    double* gmom = nullptr;     // [9][2][Bp] Kahan (sum, compensation) of the estimator quantities
     int64_t* step = nullptr;    // device step counter
     float* diag = nullptr;      // per-block max norm deviation / nan flags
 };
@@ -165,6 +173,14 @@ bool small_path_applies(int precision, int64_t N, int64_t n_lags);
 int launch_small_run(const Geometry& g, const EnsembleBuffers& b, const StepConsts& c, const twa_pump* pump,
                      double dt, int64_t n_steps, int out_cur, hipStream_t st);
 
+// correlated decay (twa_decay.hip): observation operands and the per-step
+// estimator of correlated emission; the geometry pads trajectories to a
+// multiple of the column tile
+int decay_geometry_ok(const Geometry& g);
+int alloc_decay_buffers(const Geometry& g, EnsembleBuffers& b);
+int launch_decay_ops(const Geometry& g, const double* G, const EnsembleBuffers& b, hipStream_t st);
+int launch_decay_observe(const Geometry& g, const EnsembleBuffers& b, int cur, hipStream_t st);
+
 // pump (twa_pump.hip): the Eq. (2) pump of a handle rescaled to amplitude w
 int pump_scaled(const twa_pump* base, double w, twa_pump** out);
 }  // namespace twa
@@ -177,5 +193,7 @@ struct twa_pump {
     double* F = nullptr;     // device FP64 [N][N]
     double* V = nullptr;     // device FP64 eigenvectors, column-major (column j = vector j)
     double* lam = nullptr;   // host eigenvalues ascending [N]
+    double* G = nullptr;     // device FP64 [N][N] correlated-decay matrix (model handles only); then
+                             // W holds the drift matrix W - G and F, V, lam belong to W + G
     int device = 0;
 };

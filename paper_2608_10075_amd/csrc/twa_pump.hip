@@ -138,11 +138,26 @@ done:
 
 static void pump_release(twa_pump* p) {
     if (!p) return;
+    hipFree(p->G);
     hipFree(p->W);
     hipFree(p->F);
     hipFree(p->V);
     free(p->lam);
     delete p;
+}
+
+__global__ void axpy_kernel(int64_t n, const double* a, double f, const double* b, double* out) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) out[t] = a[t] + f * b[t];
+}
+
+static bool symmetric_finite(int64_t N, const double* M) {
+    for (int64_t i = 0; i < N; ++i)
+        for (int64_t j = 0; j < N; ++j) {
+            const double a = M[i * N + j], b = M[j * N + i];
+            if (!std::isfinite(a) || std::fabs(a - b) > 1e-12 * (std::fabs(a) + std::fabs(b))) return false;
+        }
+    return true;
 }
 
 __global__ void scale_kernel(int64_t n, const double* in, double f, double* out) {
@@ -271,6 +286,82 @@ TWA_API int twa_build_pump_dense(int64_t N, const double* W_host, twa_pump** out
     return TWA_OK;
 }
 
+TWA_API int twa_build_model_dense(int64_t N, const double* W_host, const double* G_host, twa_pump** out) {
+    using namespace twa;
+    if (!out || N < 1 || !W_host || !G_host) {
+        set_error("twa_build_model_dense: need N >= 1, two matrices and an output pointer");
+        return TWA_EINVAL;
+    }
+    if (!symmetric_finite(N, W_host) || !symmetric_finite(N, G_host)) {
+        set_error("twa_build_model_dense: matrices must be finite and symmetric");
+        return TWA_EINVAL;
+    }
+    *out = nullptr;
+    const size_t bytes = (size_t)N * N * sizeof(double);
+    const int64_t n2 = N * N;
+    const unsigned nb = (unsigned)((n2 + 255) / 256);
+    int rc;
+    // the decay matrix itself must be PSD (a physical Lindbladian)
+    {
+        twa_pump* q = new twa_pump();
+        q->N = N;
+        q->w = q->alpha = NAN;
+        if (hipMalloc(&q->W, bytes) != hipSuccess) {
+            delete q;
+            set_error("twa_build_model_dense: device allocation failed");
+            return TWA_ENOMEM;
+        }
+        if (hipMemcpy(q->W, G_host, bytes, hipMemcpyHostToDevice) != hipSuccess) {
+            pump_release(q);
+            set_error("twa_build_model_dense: hipMemcpy failed");
+            return TWA_EHIP;
+        }
+        rc = factorise(q);
+        pump_release(q);
+        if (rc == TWA_ENOTPSD) set_error("twa_build_model_dense: decay matrix is not positive semidefinite");
+        if (rc) return rc;
+    }
+    twa_pump* p = new twa_pump();
+    p->N = N;
+    p->w = NAN;
+    p->alpha = NAN;
+    hipGetDevice(&p->device);
+    double* Wd = nullptr;
+    if (hipMalloc(&p->W, bytes) != hipSuccess || hipMalloc(&p->G, bytes) != hipSuccess ||
+        hipMalloc(&Wd, bytes) != hipSuccess) {
+        hipFree(Wd);
+        pump_release(p);
+        set_error("twa_build_model_dense: device allocation failed");
+        return TWA_ENOMEM;
+    }
+    if (hipMemcpy(Wd, W_host, bytes, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(p->G, G_host, bytes, hipMemcpyHostToDevice) != hipSuccess) {
+        hipFree(Wd);
+        pump_release(p);
+        set_error("twa_build_model_dense: hipMemcpy failed");
+        return TWA_EHIP;
+    }
+    // noise factor of the summed noise: sqrt(W + G); then the drift matrix W - G
+    hipLaunchKernelGGL(axpy_kernel, dim3(nb), dim3(256), 0, 0, n2, Wd, 1.0, p->G, p->W);
+    rc = hipGetLastError() == hipSuccess ? factorise(p) : TWA_EHIP;
+    if (rc == TWA_OK) {
+        hipLaunchKernelGGL(axpy_kernel, dim3(nb), dim3(256), 0, 0, n2, Wd, -1.0, p->G, p->W);
+        if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+            set_error("twa_build_model_dense: kernel failed");
+            rc = TWA_EHIP;
+        }
+    } else if (rc == TWA_EHIP) {
+        set_error("twa_build_model_dense: factorisation of W + G failed");
+    }
+    hipFree(Wd);
+    if (rc) {
+        pump_release(p);
+        return rc;
+    }
+    *out = p;
+    return TWA_OK;
+}
+
 TWA_API void twa_pump_free(twa_pump* p) { twa::pump_release(p); }
 
 TWA_API int twa_pump_info(const twa_pump* p, int64_t* N, double* lam_min, double* lam_max) {
@@ -285,11 +376,11 @@ TWA_API int twa_pump_info(const twa_pump* p, int64_t* N, double* lam_min, double
 }
 
 TWA_API int twa_pump_copy_matrix(const twa_pump* p, int which, double* out_host) {
-    if (!p || !out_host || (which != 0 && which != 1)) {
-        twa::set_error("twa_pump_copy_matrix: bad arguments");
+    if (!p || !out_host || which < 0 || which > 2 || (which == 2 && !p->G)) {
+        twa::set_error("twa_pump_copy_matrix: bad arguments (which = 2 needs a model handle)");
         return TWA_EINVAL;
     }
-    const double* src = which == 0 ? p->W : p->F;
+    const double* src = which == 0 ? p->W : which == 1 ? p->F : p->G;
     if (hipMemcpy(out_host, src, (size_t)p->N * p->N * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) {
         twa::set_error("twa_pump_copy_matrix: hipMemcpy failed");
         return TWA_EHIP;

@@ -54,6 +54,7 @@ void free_buffers(EnsembleBuffers& b);
 int alloc_buffers(const Geometry& g, bool tangents, int64_t L, int J, EnsembleBuffers& b);
 Geometry make_geometry(int precision, int cfg, int64_t N, int64_t B);
 void finalize_moments(const std::vector<double>& traj, int64_t B, twa_observables* o);
+void finalize_decay(const std::vector<double>& traj, int64_t B, twa_observables* o);
 double linewidth_of(const std::vector<std::complex<double>>& corr, double tau);
 
 // per-launch timers for the two contraction stages (primal)

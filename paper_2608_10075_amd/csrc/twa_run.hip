@@ -104,6 +104,56 @@ void finalize_moments(const std::vector<double>& traj, int64_t B, twa_observable
     o->Sz_se = se[5]; o->SpSm_se = se[6]; o->g2_se = se[7];
 }
 
+void finalize_decay(const std::vector<double>& traj, int64_t B, twa_observables* o) {
+    // traj: [B][9] per-trajectory window averages of (E2, E2^2, E2 D, Q3, R, D^2, U, V, D);
+    // intensity I = E2 + D/2 and the four-point function of SM Sec. S1 step 6, g2 = four-point / I^2
+    const int J = (int)std::min<int64_t>(32, B);
+    std::vector<double> bsum((size_t)J * 9, 0.0), bcnt((size_t)J, 0.0);
+    for (int64_t k = 0; k < B; ++k) {
+        const int j = (int)((k * J) / B);
+        for (int m = 0; m < 9; ++m) bsum[(size_t)j * 9 + m] += traj[(size_t)k * 9 + m];
+        bcnt[(size_t)j] += 1.0;
+    }
+    double tot[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int j = 0; j < J; ++j)
+        for (int m = 0; m < 9; ++m) tot[m] += bsum[(size_t)j * 9 + m];
+    auto derive = [](const double* m, double* d) {
+        const double E2 = m[0], E2E2 = m[1], E2D = m[2], Q3 = m[3], R = m[4], DD = m[5], U = m[6], V = m[7], D = m[8];
+        const double inten = E2 + 0.5 * D;
+        const double num = E2E2 + E2D + Q3 - R / 3.0 + 0.25 * (DD + U) - (4.0 / 3.0) * V;
+        d[0] = inten;
+        d[1] = num / (inten * inten);
+    };
+    double mean[9], dm[2];
+    for (int m = 0; m < 9; ++m) mean[m] = tot[m] / (double)B;
+    derive(mean, dm);
+    o->I_gen = dm[0];
+    o->g2_gen = dm[1];
+    o->I_gen_se = o->g2_gen_se = NAN;
+    if (J >= 2) {
+        std::vector<double> vals((size_t)J * 2);
+        for (int j = 0; j < J; ++j) {
+            double v[9];
+            for (int m = 0; m < 9; ++m) v[m] = (tot[m] - bsum[(size_t)j * 9 + m]) / ((double)B - bcnt[(size_t)j]);
+            derive(v, &vals[(size_t)j * 2]);
+        }
+        double se[2];
+        for (int c = 0; c < 2; ++c) {
+            double mu = 0;
+            for (int j = 0; j < J; ++j) mu += vals[(size_t)j * 2 + c];
+            mu /= J;
+            double ss = 0;
+            for (int j = 0; j < J; ++j) {
+                const double d = vals[(size_t)j * 2 + c] - mu;
+                ss += d * d;
+            }
+            se[c] = std::sqrt((double)(J - 1) / J * ss);
+        }
+        o->I_gen_se = se[0];
+        o->g2_gen_se = se[1];
+    }
+}
+
 // iterative radix-2 FFT computing sum_l c_l e^{+2 pi i k l / n}
 static void fft_pos(std::vector<std::complex<double>>& a) {
     const size_t n = a.size();
@@ -180,7 +230,8 @@ double linewidth_of(const std::vector<std::complex<double>>& corr, double tau) {
 void free_buffers(EnsembleBuffers& b) {
     void* ptrs[] = {b.A,      b.Xop,    b.Dop,  b.s[0], b.s[1],    b.dlt,     b.Y,      b.part[0],
                     b.part[1], b.g,     b.norm0, b.mom, b.tXop,    b.tDop,    b.ts[0],  b.ts[1],
-                    b.tdlt,   b.tY,     b.tpart[0], b.tpart[1], b.sm0, b.lag, b.step, b.diag, b.Sn};
+                    b.tdlt,   b.tY,     b.tpart[0], b.tpart[1], b.sm0, b.lag, b.step, b.diag, b.Sn,
+                    b.AG,     b.AGG,    b.Zop,  b.GX,   b.UZ,      b.dg,      b.gmom};
     for (void* q : ptrs) hipFree(q);
     b = EnsembleBuffers();
 }
@@ -235,6 +286,17 @@ int alloc_buffers(const Geometry& g, bool tangents, int64_t L, int J, EnsembleBu
         TWA_A(b.tpart[1], 2 * 3 * nmt * Bp * se)
     }
 #undef TWA_A
+    return TWA_OK;
+}
+
+int alloc_decay_buffers(const Geometry& g, EnsembleBuffers& b) {
+    const size_t ge = (size_t)gemm_elt_bytes(g.precision), se = (size_t)state_elt_bytes(g.precision);
+    const size_t P = (size_t)g.P, Bp = (size_t)g.Bp;
+    int rc;
+    if ((rc = dalloc(&b.AG, P * P * ge)) || (rc = dalloc(&b.AGG, P * P * ge)) || (rc = dalloc(&b.Zop, Bp * P * ge)) ||
+        (rc = dalloc(&b.GX, 2 * Bp * P * se)) || (rc = dalloc(&b.UZ, Bp * P * se)) || (rc = dalloc(&b.dg, P * se)) ||
+        (rc = dalloc((void**)&b.gmom, 18 * Bp * sizeof(double))))
+        return rc;
     return TWA_OK;
 }
 

@@ -47,11 +47,12 @@ struct Plan {
 };
 
 int one_step(const Geometry& g, EnsembleBuffers& b, const StepConsts& c, int& cur, const StepKind& k,
-             GemmTimers* tm, hipStream_t st) {
+             bool decay, GemmTimers* tm, hipStream_t st) {
     int rc;
     if ((rc = launch_step_kernels(g, b, c, cur, k.tan_active, tm, st))) return rc;
     if (k.seed_after && (rc = launch_seed_tangents(g, b, 1 - cur, st))) return rc;
     if (k.observe && (rc = launch_observe(g, b, c, 1 - cur, k.tobs, st))) return rc;
+    if (decay && k.observe && (rc = launch_decay_observe(g, b, 1 - cur, st))) return rc;
     cur = 1 - cur;
     return TWA_OK;
 }
@@ -69,11 +70,16 @@ struct GraphCache {
 
 int run_single(const twa_params* p, int64_t n_traj, double dt, int64_t n_steps, uint64_t seed,
                twa_observables* out, const twa_outputs* outs) {
+    const bool decay = p && p->pump && p->pump->G;
     if (!p || !p->pump || !out || n_traj < 1 || n_steps < 0 || !(dt > 0) || !std::isfinite(dt) ||
-        !(p->gamma > 0) || !std::isfinite(p->gamma) ||
+        (!decay && (!(p->gamma > 0) || !std::isfinite(p->gamma))) ||
         (p->integrator != TWA_INT_HEUN && p->integrator != TWA_INT_SIB)) {
         set_error("twa_run: need params with a pump, n_traj >= 1, n_steps >= 0, dt > 0, gamma > 0, "
                   "integrator TWA_INT_HEUN or TWA_INT_SIB");
+        return TWA_EINVAL;
+    }
+    if (decay && p->n_lags > 0) {
+        set_error("twa_run: the two-time correlation is not defined for correlated decay (n_lags must be 0)");
         return TWA_EINVAL;
     }
     if (p->integrator == TWA_INT_SIB && p->n_lags > 0) {
@@ -107,7 +113,12 @@ int run_single(const twa_params* p, int64_t n_traj, double dt, int64_t n_steps, 
     }
     Geometry g = make_geometry(p->precision, cfg, N, B);
     g.integrator = p->integrator;
-    const bool fused = p->tile_config < 0 && small_path_applies(p->precision, N, L);
+    if (decay) {
+        // the packed s^z contraction covers Bp / 2 column pairs
+        g.Bp = round_up(B, tile_cfg(cfg).nt);
+        g.C2 = 2 * g.Bp;
+    }
+    const bool fused = p->tile_config < 0 && !decay && small_path_applies(p->precision, N, L);
     const int J = (int)std::min<int64_t>(32, B);
     const bool tangents = L > 0;
 
@@ -127,13 +138,14 @@ int run_single(const twa_params* p, int64_t n_traj, double dt, int64_t n_steps, 
     GemmTimers* tm = nullptr;
     GraphCache gc;
     int rc = TWA_OK;
-    std::vector<double> hmom, hlag;
+    std::vector<double> hmom, hlag, hgen;
     std::vector<float> hdiag;
     const int nblk = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (B * N + 255) / 256));
 
     StepConsts c;
-    c.c1 = 0.5 * p->gamma * dt;
-    c.c2 = std::sqrt(p->gamma * dt);
+    // a decay matrix replaces the collective terms (it sits in the operand)
+    c.c1 = decay ? 0.0 : 0.5 * p->gamma * dt;
+    c.c2 = decay ? 0.0 : std::sqrt(p->gamma * dt);
     c.s0z = p->s0z;
     c.key0 = (uint32_t)(seed & 0xffffffffu);
     c.key1 = (uint32_t)(seed >> 32);
@@ -165,6 +177,11 @@ int run_single(const twa_params* p, int64_t n_traj, double dt, int64_t n_steps, 
 
     TWA_TRY(alloc_buffers(g, tangents, L, J, b));
     TWA_TRY(launch_build_A(g, pump->W, pump->F, dt, b.A, st));
+    if (decay) {
+        TWA_TRY(decay_geometry_ok(g));
+        TWA_TRY(alloc_decay_buffers(g, b));
+        TWA_TRY(launch_decay_ops(g, pump->G, b, st));
+    }
     if (p->init_state) {
         TWA_HTRY(hipMalloc(&init_dev, (size_t)3 * B * N * sizeof(double)));
         TWA_HTRY(hipMemcpyAsync(init_dev, p->init_state, (size_t)3 * B * N * sizeof(double), hipMemcpyHostToDevice, st));
@@ -202,7 +219,7 @@ int run_single(const twa_params* p, int64_t n_traj, double dt, int64_t n_steps, 
                 TWA_HTRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
                 int cc = cur;
                 int crc = TWA_OK;
-                for (int s = 0; s < GS && crc == TWA_OK; ++s) crc = one_step(g, b, c, cc, k, nullptr, st);
+                for (int s = 0; s < GS && crc == TWA_OK; ++s) crc = one_step(g, b, c, cc, k, decay, nullptr, st);
                 hipError_t ee = hipStreamEndCapture(st, &gr);
                 if (crc != TWA_OK) {
                     rc = crc;
@@ -217,7 +234,7 @@ int run_single(const twa_params* p, int64_t n_traj, double dt, int64_t n_steps, 
             TWA_HTRY(hipGraphLaunch(it->second, st));
             n += GS;   // GS even: cur unchanged
         } else {
-            TWA_TRY(one_step(g, b, c, cur, k, tm, st));
+            TWA_TRY(one_step(g, b, c, cur, k, decay, tm, st));
             n += 1;
         }
     }
@@ -234,6 +251,10 @@ int run_single(const twa_params* p, int64_t n_traj, double dt, int64_t n_steps, 
         for (size_t i = 0; i < tmp.size(); ++i) hmom[i] = tmp[i];
     }
     TWA_HTRY(hipMemcpyAsync(hdiag.data(), b.diag, hdiag.size() * sizeof(float), hipMemcpyDeviceToHost, st));
+    if (decay) {
+        hgen.resize((size_t)18 * g.Bp);
+        TWA_HTRY(hipMemcpyAsync(hgen.data(), b.gmom, hgen.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    }
     if (L > 0) {
         hlag.resize((size_t)L * J * 6);
         TWA_HTRY(hipMemcpyAsync(hlag.data(), b.lag, hlag.size() * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -268,7 +289,7 @@ int run_single(const twa_params* p, int64_t n_traj, double dt, int64_t n_steps, 
         out->n_lags = L;
         out->lag_stride = stride;
         out->max_norm_dev = mx;
-        out->step_criterion = std::max(p->gamma * (double)N, pump->lam_max) * dt;
+        out->step_criterion = (decay ? pump->lam_max : std::max(p->gamma * (double)N, pump->lam_max)) * dt;
         out->nan_flag = nan ? 1 : 0;
         out->tile_config = fused ? TWA_TILE_FUSED : cfg;
         out->kernel_ms = loop_ms;
@@ -284,7 +305,22 @@ int run_single(const twa_params* p, int64_t n_traj, double dt, int64_t n_steps, 
         // response copies: 2 copies x 2*N*N*(2B) per stage
         const double nb = (double)N * (double)N * (double)B;
         const double tan_steps = L > 0 ? (double)((L - 1) * stride) : 0.0;
-        out->gemm_flops = (double)n_steps * 12.0 * nb + tan_steps * 16.0 * nb;
+        // correlated decay: G [s^x, s^y] and (G o G) s^z per observed state
+        out->gemm_flops = (double)n_steps * 12.0 * nb + tan_steps * 16.0 * nb + (decay ? (double)ns * 6.0 * nb : 0.0);
+        out->I_gen = out->g2_gen = out->I_gen_se = out->g2_gen_se = NAN;
+        if (decay) {
+            std::vector<double> tg((size_t)B * 9);
+            for (int64_t k = 0; k < B; ++k)
+                for (int m = 0; m < 9; ++m) {
+                    const double s = hgen[(size_t)(2 * m) * g.Bp + k], cmp = hgen[(size_t)(2 * m + 1) * g.Bp + k];
+                    const double v = ns > 0 ? (s - cmp) / (double)ns : NAN;
+                    tg[(size_t)k * 9 + m] = v;
+                    if (ns > 0 && !std::isfinite(v)) nan = true;
+                }
+            finalize_decay(tg, B, out);
+            if (outs && outs->traj_gen) std::memcpy(outs->traj_gen, tg.data(), tg.size() * sizeof(double));
+            out->nan_flag = nan ? 1 : 0;
+        }
         out->linewidth = NAN;
         out->linewidth_sym = NAN;
         if (L > 0) {
