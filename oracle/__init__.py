@@ -39,6 +39,9 @@ GPU-accelerated Truncated Wigner dynamics"):
                      the Perspectives): the step's matrices W - G and
                      sqrt(W + G), and the intensity and four-point function of
                      correlated emission (SM Sec. S1 step 6) with jackknife.
+* ``toeplitz``    -- not in the paper: Eq. (2) applied through its circulant
+                     embedding (FFT products) with the pump noise drawn from the
+                     embedding (equal in law to the dense path's).
 * ``protocol``    -- the paper's time-step criterion, preparation time and
                      window, and the threshold / g2-minimum searches.
 * ``closed_forms``-- the alpha=0 closed forms (noiseless superradiant decay and

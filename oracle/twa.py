@@ -15,7 +15,9 @@ Follows SM Sec. S1 of the paper step by step:
 and the two-time correlation (Eq. (S3) and the three-copy response that
 follows it).  With ``RunConfig.decay`` the collective decay is replaced by a
 correlated-decay matrix (``oracle.decay``) and the window also accumulates the
-nine per-trajectory quantities of the correlated-emission estimator.
+nine per-trajectory quantities of the correlated-emission estimator.  With
+``RunConfig.toeplitz`` the pump is applied through its circulant embedding
+(``oracle.toeplitz``), which also supplies the pump noise.
 
 Readings where the paper is silent (listed with the others in the design
 notes of the repository):
@@ -45,6 +47,7 @@ import numpy as np
 
 from . import decay as odecay
 from . import philox
+from . import toeplitz as otoe
 from .pump import Pump, build_pump
 
 
@@ -72,6 +75,8 @@ class RunConfig:
                                            # so any subset of an ensemble can be integrated alone)
     decay: Optional[np.ndarray] = None     # (N, N) symmetric PSD correlated-decay matrix G; replaces
                                            # the collective decay (gamma unused), see oracle.decay
+    toeplitz: bool = False                 # apply Eq. (2) through its circulant embedding and draw
+                                           # the pump noise from it (oracle.toeplitz)
 
     def resolved_burnin(self) -> int:
         return self.n_steps // 2 if self.burnin is None else int(self.burnin)
@@ -108,6 +113,12 @@ def collective_sums(x, y, z):
     return x.sum(axis=1), y.sum(axis=1), z.sum(axis=1)
 
 
+def _matvec(W, v):
+    """sum_j W_ij v_j for every row of v: a dense matrix, or an operator with
+    ``apply`` (the circulant embedding of Eq. (2))."""
+    return W.apply(v) if hasattr(W, "apply") else v @ W.T
+
+
 def increment(state, W, gamma, dt, dxi, dchi):
     """One-step increment of Eq. (S1) at a given state with given noise increments.
 
@@ -119,8 +130,8 @@ def increment(state, W, gamma, dt, dxi, dchi):
     x, y, z = state
     Sx = x.sum(axis=1)[:, None]
     Sy = y.sum(axis=1)[:, None]
-    hx = (0.5 * gamma * Sx - 0.5 * (x @ W.T)) * dt + dxi[0][:, None] - dchi[0]
-    hy = (0.5 * gamma * Sy - 0.5 * (y @ W.T)) * dt + dxi[1][:, None] - dchi[1]
+    hx = (0.5 * gamma * Sx - 0.5 * _matvec(W, x)) * dt + dxi[0][:, None] - dchi[0]
+    hy = (0.5 * gamma * Sy - 0.5 * _matvec(W, y)) * dt + dxi[1][:, None] - dchi[1]
     return z * hx, z * hy, -(x * hx + y * hy), (hx, hy)
 
 
@@ -129,8 +140,8 @@ def increment_tangent(state, dstate, fields, W, gamma, dt):
     x, y, z = state
     dx, dy, dz = dstate
     hx, hy = fields
-    dhx = (0.5 * gamma * dx.sum(axis=1)[:, None] - 0.5 * (dx @ W.T)) * dt
-    dhy = (0.5 * gamma * dy.sum(axis=1)[:, None] - 0.5 * (dy @ W.T)) * dt
+    dhx = (0.5 * gamma * dx.sum(axis=1)[:, None] - 0.5 * _matvec(W, dx)) * dt
+    dhy = (0.5 * gamma * dy.sum(axis=1)[:, None] - 0.5 * _matvec(W, dy)) * dt
     return (dz * hx + z * dhx,
             dz * hy + z * dhy,
             -(dx * hx + x * dhx + dy * hy + y * dhy))
@@ -144,10 +155,13 @@ def noise_increments(cfg: RunConfig, pump: Pump, step: int):
         zN = np.zeros((B, n))
         return (z1, z1), (zN, zN)
     gx, gy = philox.collective_noise(cfg.seed, step, B, cfg.point, cfg.traj)
-    zx, zy = philox.pump_noise(cfg.seed, step, B, n, cfg.point, cfg.traj)
     sg = np.sqrt(cfg.gamma * cfg.dt)
     sq = np.sqrt(cfg.dt)
     dxi = (sg * gx, sg * gy)
+    if isinstance(pump, otoe.ToeplitzPump):
+        ex, ey = pump.noise(pump.normals(cfg.seed, step, B, cfg.point, cfg.traj))
+        return dxi, (sq * ex, sq * ey)
+    zx, zy = philox.pump_noise(cfg.seed, step, B, n, cfg.point, cfg.traj)
     dchi = (sq * (zx @ pump.F.T), sq * (zy @ pump.F.T))
     return dxi, dchi
 
@@ -238,6 +252,10 @@ def run(cfg: RunConfig, pump: Optional[Pump] = None) -> RunResult:
     """Integrate all trajectories and accumulate the observables."""
     if pump is None:
         pump = build_pump(cfg.n_spin, cfg.w, cfg.alpha)
+    if cfg.toeplitz:
+        if cfg.decay is not None:
+            raise ValueError("the circulant embedding applies to the pump of Eq. (2) only")
+        pump = otoe.ToeplitzPump(cfg.n_spin, cfg.w, cfg.alpha)
     G = None
     if cfg.decay is not None:
         if cfg.n_lags > 0:
@@ -245,7 +263,7 @@ def run(cfg: RunConfig, pump: Optional[Pump] = None) -> RunResult:
         G = np.asarray(cfg.decay, dtype=np.float64)
         pump = odecay.model_pump(pump.W, G)
         cfg = replace(cfg, gamma=0.0)    # the matrix replaces the collective terms
-    W = pump.W
+    W = pump if cfg.toeplitz else pump.W
     B, T = cfg.n_traj, cfg.n_steps
     burn = cfg.resolved_burnin()
     if cfg.init_state is not None:
