@@ -133,6 +133,27 @@ def adjoint_cost(twa, steps=2048, reps=1):
             "gradients": grads}
 
 
+def toeplitz_rate(twa, N, w, alpha, B, dt, T, dense_value):
+    """The same workload through the circulant embedding of Eq. (2) (FFT
+    drift and circulant pump noise, equal in law to the dense path), FP32,
+    one full run after a short warm-up run."""
+    import torch
+    light = twa.build_pump_toeplitz(N, w, alpha)
+    twa.run(light, B, dt, 256, seed=0, precision="fp32", pump_path="toeplitz")
+    torch.cuda.synchronize()
+    t0 = time.time()
+    r = twa.run(light, B, dt, T, seed=0, precision="fp32", pump_path="toeplitz")
+    torch.cuda.synchronize()
+    wall = time.time() - t0
+    value = B * N * T / wall
+    M = 256
+    while M < 2 * N - 2:
+        M *= 2
+    return {"value": value, "unit": "trajectory-atom-steps/s", "precision": "fp32", "wall_s": wall,
+            "kernel_ms": r.obs["kernel_ms"], "speedup_vs_dense": value / dense_value, "embedding_size": M,
+            "observables": {k: r.obs[k] for k in ("Sz", "SpSm", "g2", "Sz_se", "SpSm_se", "g2_se")}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -142,6 +163,7 @@ def main():
     ap.add_argument("--tile-config", type=int, default=-1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-toeplitz", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (trajectories would shard "
@@ -217,6 +239,9 @@ def main():
                                              "step_criterion")},
         "tile_config": obs["tile_config"],
     }
+    if not args.no_toeplitz:
+        print("[bench] Toeplitz fast path on the same workload (FP32)", file=sys.stderr, flush=True)
+        line["toeplitz_path"] = toeplitz_rate(twa, N, w, alpha, B, dt, T, value)
     if not args.no_adjoint:
         print("[bench] adjoint cost ratio (N=2000, FP32)", file=sys.stderr, flush=True)
         line["adjoint"] = adjoint_cost(twa)

@@ -62,6 +62,22 @@ extern "C" {
 
 /* tile_config reported when the fused small-N kernel integrated the run */
 #define TWA_TILE_FUSED  99
+/* tile_config reported when the Toeplitz fast path integrated the run */
+#define TWA_TILE_TOEPLITZ 98
+
+/* ---- how the pump of Eq. (2) is applied -------------------------------- */
+#define TWA_PUMP_DENSE    0 /* MFMA contractions with W and its PSD square root F */
+#define TWA_PUMP_TOEPLITZ 1 /* not in the paper: circulant embedding of the Toeplitz
+                               matrix of Eq. (2) (first column c(min(j, M-j)),
+                               c(d) = w/(1+d)^alpha, M = max(256, 2^ceil(log2(2N-2))),
+                               PSD for this convex decreasing c); W s by FFT
+                               products and the pump noise drawn from the
+                               embedding, IDFT(sqrt(lam M) eps)[:N] with complex
+                               normals eps from Philox tag 3 (eps_k and
+                               eps_{k+M/2} from one call): equal in law to the
+                               dense path, not pathwise.  Heun, FP64 (N <= 8193)
+                               or FP32 (N <= 16385), a pump from twa_build_pump,
+                               no two-time lags.  O(M log M) per trajectory-step */
 
 /* ---- integrators ------------------------------------------------------ */
 #define TWA_INT_HEUN    0   /* stochastic Heun, Stratonovich reading of Eq. (S1) */
@@ -122,6 +138,17 @@ TWA_API int twa_build_pump_dense(int64_t N, const double* W_host, twa_pump** out
  */
 TWA_API int twa_build_model_dense(int64_t N, const double* W_host, const double* G_host, twa_pump** out);
 
+/*
+ * twa_build_pump_toeplitz -- a light handle of Eq. (2) for the Toeplitz fast
+ * path only (twa_params pump_path = TWA_PUMP_TOEPLITZ): no dense matrices, no
+ * eigendecomposition, O(1) device memory.  lam_max is the largest eigenvalue
+ * of the circulant embedding (an upper bound of the largest channel rate, by
+ * interlacing), lam_min is NaN.  Rejected by the dense path, twa_adjoint,
+ * twa_protocol and twa_pump_copy_matrix.  Errors: TWA_EINVAL (N outside
+ * 1 .. 16385, non-finite or negative w or alpha, NULL out).
+ */
+TWA_API int twa_build_pump_toeplitz(int64_t N, double w, double alpha, twa_pump** out);
+
 /* Releases a handle from twa_build_pump*; NULL is ignored. */
 TWA_API void twa_pump_free(twa_pump* p);
 
@@ -167,6 +194,7 @@ typedef struct twa_params {
     int32_t adjoint_objectives; /* twa_adjoint: mask of 1 (<S+S->) and 2 (g2); 0 =  */
                              /* both.  The reverse sweep carries one copy per       */
                              /* objective; unselected gradients are returned NaN   */
+    int32_t pump_path;       /* twa_run: TWA_PUMP_DENSE (default) or TWA_PUMP_TOEPLITZ */
 } twa_params;
 
 /* Fills *p with defaults: gamma 1, s0z +1, burnin -1, Heun, FP32, no lags,

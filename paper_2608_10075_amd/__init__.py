@@ -25,6 +25,7 @@ LIB_PATH = os.path.join(_HERE, "libtwa.so")
 TWA_OK, TWA_EINVAL, TWA_ENOMEM, TWA_EHIP, TWA_ENOTPSD, TWA_EUNSTABLE = 0, -1, -2, -3, -4, -5
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "fp16": 3}
 INTEGRATORS = {"heun": 0, "sib": 1}
+PUMP_PATHS = {"dense": 0, "toeplitz": 1}
 
 
 class TWAError(RuntimeError):
@@ -38,7 +39,8 @@ class _Params(C.Structure):
                 ("integrator", C.c_int32), ("precision", C.c_int32), ("n_lags", C.c_int64),
                 ("lag_stride", C.c_int64), ("point", C.c_int32), ("tile_config", C.c_int32),
                 ("stream", C.c_void_p), ("init_state", C.POINTER(C.c_double)), ("timing", C.c_int32),
-                ("use_graph", C.c_int32), ("kappa", C.c_double), ("adjoint_objectives", C.c_int32)]
+                ("use_graph", C.c_int32), ("kappa", C.c_double), ("adjoint_objectives", C.c_int32),
+                ("pump_path", C.c_int32)]
 
 
 _OBS_DOUBLES1 = ["T2", "T3", "T4", "Z", "ZZ", "Sz", "SpSm", "g2",
@@ -94,6 +96,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.twa_version.restype = C.c_char_p
     lib.twa_build_pump.argtypes = [C.c_int64, C.c_double, C.c_double, C.POINTER(P)]
     lib.twa_build_pump_dense.argtypes = [C.c_int64, C.POINTER(C.c_double), C.POINTER(P)]
+    lib.twa_build_pump_toeplitz.argtypes = [C.c_int64, C.c_double, C.c_double, C.POINTER(P)]
     lib.twa_build_model_dense.argtypes = [C.c_int64, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(P)]
     lib.twa_pump_free.argtypes = [P]
     lib.twa_pump_free.restype = None
@@ -119,7 +122,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.twa_g2_min.argtypes = [C.c_int64, C.c_double, C.POINTER(_Params), C.c_int64, C.c_uint64, C.c_int32,
                                C.c_double, C.c_double, C.c_double, C.c_int32, C.POINTER(C.c_double),
                                C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double)]
-    for name in ("twa_build_pump", "twa_build_pump_dense", "twa_build_model_dense", "twa_pump_info", "twa_pump_copy_matrix", "twa_run",
+    for name in ("twa_build_pump", "twa_build_pump_dense", "twa_build_pump_toeplitz", "twa_build_model_dense", "twa_pump_info", "twa_pump_copy_matrix", "twa_run",
                  "twa_run_batch", "twa_adjoint", "twa_philox", "twa_noise", "twa_protocol", "twa_find_threshold",
                  "twa_g2_min"):
         getattr(lib, name).restype = C.c_int
@@ -156,10 +159,12 @@ class Pump:
     With ``decay`` (and ``dense``): a model handle for correlated decay."""
 
     def __init__(self, N: int, w: float = None, alpha: float = None, dense: Optional[np.ndarray] = None,
-                 decay: Optional[np.ndarray] = None):
+                 decay: Optional[np.ndarray] = None, toeplitz_only: bool = False):
         h = C.c_void_p()
         self.has_decay = decay is not None
-        if decay is not None:
+        if toeplitz_only:
+            _check(_lib.twa_build_pump_toeplitz(int(N), float(w), float(alpha), C.byref(h)))
+        elif decay is not None:
             W = np.ascontiguousarray(dense, dtype=np.float64)
             G = np.ascontiguousarray(decay, dtype=np.float64)
             assert W.shape == (N, N) and G.shape == (N, N)
@@ -206,6 +211,11 @@ def build_pump(N: int, w: float, alpha: float) -> Pump:
     return Pump(N, w, alpha)
 
 
+def build_pump_toeplitz(N: int, w: float, alpha: float) -> Pump:
+    """twa_build_pump_toeplitz: Eq. (2) for the Toeplitz fast path only."""
+    return Pump(N, w, alpha, toeplitz_only=True)
+
+
 def build_model(W: np.ndarray, decay: np.ndarray) -> Pump:
     """twa_build_model_dense: pump matrix W and correlated-decay matrix G."""
     W = np.asarray(W, dtype=np.float64)
@@ -233,12 +243,15 @@ def run(pump: Pump, n_traj: int, dt: float, n_steps: int, seed: int = 0, *, gamm
         point: int = 0, tile_config: int = -1, init_state: Optional[np.ndarray] = None, timing: bool = False,
         use_graph: bool = True, kappa: float = 0.25, stream=None, want_traj: bool = False,
         want_final_state: bool = False, want_lags: bool = False, allow_unstable: bool = False,
-        integrator: str = "heun") -> RunResult:
+        integrator: str = "heun", pump_path: str = "dense") -> RunResult:
     """twa_run: n_traj trajectories of Eq. (S1), n_steps steps of size dt of the
-    stochastic Heun ("heun") or semi-implicit midpoint ("sib") integrator."""
+    stochastic Heun ("heun") or semi-implicit midpoint ("sib") integrator; the
+    pump applied by dense contractions ("dense") or through the circulant
+    embedding of Eq. (2) ("toeplitz")."""
     p = _Params()
     _lib.twa_params_default(C.byref(p))
     p.pump = pump.handle
+    p.pump_path = PUMP_PATHS[pump_path]
     p.integrator = INTEGRATORS[integrator]
     p.gamma, p.s0z, p.burnin = gamma, s0z, burnin
     p.precision = PRECISIONS[precision]

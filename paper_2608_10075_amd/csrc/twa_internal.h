@@ -181,6 +181,15 @@ int alloc_decay_buffers(const Geometry& g, EnsembleBuffers& b);
 int launch_decay_ops(const Geometry& g, const double* G, const EnsembleBuffers& b, hipStream_t st);
 int launch_decay_observe(const Geometry& g, const EnsembleBuffers& b, int cur, hipStream_t st);
 
+// Toeplitz fast path (twa_toeplitz.hip): circulant embedding of Eq. (2), one
+// workgroup per trajectory over chunks of steps
+int toeplitz_embedding_log2(int64_t N);
+double toeplitz_spectrum_max(int64_t N, double w, double alpha);
+int64_t toeplitz_max_n(int precision);
+int toeplitz_tables(const Geometry& g, double w, double alpha, double dt, void** tw, void** spec);
+int launch_toeplitz_run(const Geometry& g, const EnsembleBuffers& b, const StepConsts& c, const void* tw,
+                        const void* spec, int64_t n_steps, int cur, hipStream_t st);
+
 // pump (twa_pump.hip): the Eq. (2) pump of a handle rescaled to amplitude w
 int pump_scaled(const twa_pump* base, double w, twa_pump** out);
 }  // namespace twa

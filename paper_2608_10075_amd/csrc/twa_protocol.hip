@@ -57,6 +57,10 @@ TWA_API int twa_protocol(const twa_pump* pump, double gamma, double cfl, int32_t
         set_error("twa_protocol: need a pump, an output, gamma > 0 and 0 < cfl < 0.05");
         return TWA_EINVAL;
     }
+    if (!std::isfinite(pump->lam_min)) {
+        set_error("twa_protocol: needs the channel rates of a dense pump (twa_build_pump or twa_build_pump_dense)");
+        return TWA_EINVAL;
+    }
     const double N = (double)pump->N;
     twa_protocol_t r;
     std::memset(&r, 0, sizeof(r));

@@ -362,6 +362,25 @@ TWA_API int twa_build_model_dense(int64_t N, const double* W_host, const double*
     return TWA_OK;
 }
 
+TWA_API int twa_build_pump_toeplitz(int64_t N, double w, double alpha, twa_pump** out) {
+    using namespace twa;
+    if (!out || N < 1 || N > toeplitz_max_n(TWA_PREC_FP32) || !std::isfinite(w) || !std::isfinite(alpha) || w < 0 ||
+        alpha < 0) {
+        set_error("twa_build_pump_toeplitz: need 1 <= N <= 16385, finite w >= 0, finite alpha >= 0 and an output "
+                  "pointer");
+        return TWA_EINVAL;
+    }
+    twa_pump* p = new twa_pump();
+    p->N = N;
+    p->w = w;
+    p->alpha = alpha;
+    p->lam_min = NAN;
+    p->lam_max = toeplitz_spectrum_max(N, w, alpha);
+    hipGetDevice(&p->device);
+    *out = p;
+    return TWA_OK;
+}
+
 TWA_API void twa_pump_free(twa_pump* p) { twa::pump_release(p); }
 
 TWA_API int twa_pump_info(const twa_pump* p, int64_t* N, double* lam_min, double* lam_max) {
@@ -381,6 +400,10 @@ TWA_API int twa_pump_copy_matrix(const twa_pump* p, int which, double* out_host)
         return TWA_EINVAL;
     }
     const double* src = which == 0 ? p->W : which == 1 ? p->F : p->G;
+    if (!src) {
+        twa::set_error("twa_pump_copy_matrix: the handle holds no dense matrices (Toeplitz handle)");
+        return TWA_EINVAL;
+    }
     if (hipMemcpy(out_host, src, (size_t)p->N * p->N * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) {
         twa::set_error("twa_pump_copy_matrix: hipMemcpy failed");
         return TWA_EHIP;

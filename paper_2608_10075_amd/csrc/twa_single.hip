@@ -78,6 +78,23 @@ int run_single(const twa_params* p, int64_t n_traj, double dt, int64_t n_steps, 
                   "integrator TWA_INT_HEUN or TWA_INT_SIB");
         return TWA_EINVAL;
     }
+    const bool toep = p->pump_path == TWA_PUMP_TOEPLITZ;
+    if (p->pump_path != TWA_PUMP_DENSE && !toep) {
+        set_error("twa_run: pump_path must be TWA_PUMP_DENSE or TWA_PUMP_TOEPLITZ");
+        return TWA_EINVAL;
+    }
+    if (toep && (decay || !std::isfinite(p->pump->w) || !std::isfinite(p->pump->alpha) || p->n_lags > 0 ||
+                 p->integrator != TWA_INT_HEUN ||
+                 (p->precision != TWA_PREC_FP64 && p->precision != TWA_PREC_FP32) ||
+                 p->pump->N > toeplitz_max_n(p->precision))) {
+        set_error("twa_run: the Toeplitz path needs a pump from twa_build_pump, Heun, FP64 (N <= 8193) or FP32 "
+                  "(N <= 16385) and no two-time lags");
+        return TWA_EINVAL;
+    }
+    if (!toep && !p->pump->W) {
+        set_error("twa_run: a handle from twa_build_pump_toeplitz runs only with pump_path = TWA_PUMP_TOEPLITZ");
+        return TWA_EINVAL;
+    }
     if (decay && p->n_lags > 0) {
         set_error("twa_run: the two-time correlation is not defined for correlated decay (n_lags must be 0)");
         return TWA_EINVAL;
@@ -106,7 +123,7 @@ int run_single(const twa_params* p, int64_t n_traj, double dt, int64_t n_steps, 
             return TWA_EINVAL;
         }
     }
-    int cfg = p->tile_config >= 0 ? p->tile_config : pick_tile_cfg(p->precision, N, B);
+    int cfg = toep ? 0 : p->tile_config >= 0 ? p->tile_config : pick_tile_cfg(p->precision, N, B);
     if (cfg >= n_tile_cfgs() || (p->precision == TWA_PREC_FP64 && cfg > 3)) {
         set_error("twa_run: unknown tile configuration");
         return TWA_EINVAL;
@@ -118,7 +135,7 @@ int run_single(const twa_params* p, int64_t n_traj, double dt, int64_t n_steps, 
         g.Bp = round_up(B, tile_cfg(cfg).nt);
         g.C2 = 2 * g.Bp;
     }
-    const bool fused = p->tile_config < 0 && !decay && small_path_applies(p->precision, N, L);
+    const bool fused = p->tile_config < 0 && !decay && !toep && small_path_applies(p->precision, N, L);
     const int J = (int)std::min<int64_t>(32, B);
     const bool tangents = L > 0;
 
@@ -134,6 +151,7 @@ int run_single(const twa_params* p, int64_t n_traj, double dt, int64_t n_steps, 
     EnsembleBuffers b;
     double* init_dev = nullptr;
     double* export_dev = nullptr;
+    void *toep_tw = nullptr, *toep_spec = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     GemmTimers* tm = nullptr;
     GraphCache gc;
@@ -176,7 +194,10 @@ int run_single(const twa_params* p, int64_t n_traj, double dt, int64_t n_steps, 
     } while (0)
 
     TWA_TRY(alloc_buffers(g, tangents, L, J, b));
-    TWA_TRY(launch_build_A(g, pump->W, pump->F, dt, b.A, st));
+    if (toep)
+        TWA_TRY(toeplitz_tables(g, pump->w, pump->alpha, dt, &toep_tw, &toep_spec));
+    else
+        TWA_TRY(launch_build_A(g, pump->W, pump->F, dt, b.A, st));
     if (decay) {
         TWA_TRY(decay_geometry_ok(g));
         TWA_TRY(alloc_decay_buffers(g, b));
@@ -205,6 +226,11 @@ int run_single(const twa_params* p, int64_t n_traj, double dt, int64_t n_steps, 
         // one launch integrates every step (short chains are bound by per-step latency)
         cur = (int)(n_steps & 1);
         TWA_TRY(launch_small_run(g, b, c, pump, dt, n_steps, cur, st));
+        n = n_steps;
+    }
+    if (toep) {
+        // one workgroup per trajectory, state updated in place
+        TWA_TRY(launch_toeplitz_run(g, b, c, toep_tw, toep_spec, n_steps, cur, st));
         n = n_steps;
     }
     while (n < n_steps) {
@@ -291,7 +317,7 @@ int run_single(const twa_params* p, int64_t n_traj, double dt, int64_t n_steps, 
         out->max_norm_dev = mx;
         out->step_criterion = (decay ? pump->lam_max : std::max(p->gamma * (double)N, pump->lam_max)) * dt;
         out->nan_flag = nan ? 1 : 0;
-        out->tile_config = fused ? TWA_TILE_FUSED : cfg;
+        out->tile_config = fused ? TWA_TILE_FUSED : toep ? TWA_TILE_TOEPLITZ : cfg;
         out->kernel_ms = loop_ms;
         if (tm) {
             tm->s1.harvest(st);
@@ -306,7 +332,9 @@ int run_single(const twa_params* p, int64_t n_traj, double dt, int64_t n_steps, 
         const double nb = (double)N * (double)N * (double)B;
         const double tan_steps = L > 0 ? (double)((L - 1) * stride) : 0.0;
         // correlated decay: G [s^x, s^y] and (G o G) s^z per observed state
-        out->gemm_flops = (double)n_steps * 12.0 * nb + tan_steps * 16.0 * nb + (decay ? (double)ns * 6.0 * nb : 0.0);
+        out->gemm_flops = toep ? 0.0
+                               : (double)n_steps * 12.0 * nb + tan_steps * 16.0 * nb +
+                                     (decay ? (double)ns * 6.0 * nb : 0.0);
         out->I_gen = out->g2_gen = out->I_gen_se = out->g2_gen_se = NAN;
         if (decay) {
             std::vector<double> tg((size_t)B * 9);
@@ -360,6 +388,8 @@ cleanup:
     if (e1) hipEventDestroy(e1);
     hipFree(init_dev);
     hipFree(export_dev);
+    hipFree(toep_tw);
+    hipFree(toep_spec);
     free_buffers(b);
     if (own) hipStreamDestroy(own);
 #undef TWA_TRY
