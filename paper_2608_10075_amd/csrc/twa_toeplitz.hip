@@ -163,16 +163,30 @@ __device__ __forceinline__ void pass(S (&re)[R], S (&im)[R], int t, const typena
         for (int g = 0; g < G; ++g) {
             const int j = tq + g * T;
             const int qs = (j & (NS - 1)) * (M / (NS * RAD));
+            // w^r for r = 1 .. RAD-1: a table product at r = 1 and at every
+            // fourth r, the others by one more factor w (at most three
+            // roundings from a table value), a quarter of the LDS reads
+            S w1x = 0, w1y = 0, wx = 0, wy = 0;
 #pragma unroll
             for (int r = 1; r < RAD; ++r) {
-                const int q = r * qs;
-                const typename V2<S>::T a = twh[q >> 6], b = twl[q & 63];
-                const S wx = a.x * b.x - a.y * b.y;
-                const S wy0 = a.x * b.y + a.y * b.x;
-                const S wy = INV ? -wy0 : wy0;
+                if (r == 1 || (r & 3) == 0) {
+                    const int q = r * qs;
+                    const typename V2<S>::T a = twh[q >> 6], b = twl[q & 63];
+                    wx = a.x * b.x - a.y * b.y;
+                    wy = a.x * b.y + a.y * b.x;
+                    if (r == 1) {
+                        w1x = wx;
+                        w1y = wy;
+                    }
+                } else {
+                    const S nx = wx * w1x - wy * w1y;
+                    wy = wx * w1y + wy * w1x;
+                    wx = nx;
+                }
+                const S vy = INV ? -wy : wy;
                 const S xr = re[g * RAD + r], xi = im[g * RAD + r];
-                re[g * RAD + r] = xr * wx - xi * wy;
-                im[g * RAD + r] = xr * wy + xi * wx;
+                re[g * RAD + r] = xr * wx - xi * vy;
+                im[g * RAD + r] = xr * vy + xi * wx;
                 if ((r & 3) == 3) SCHED_FENCE();
             }
         }
