@@ -262,13 +262,41 @@ __device__ __forceinline__ int after(int t, const S (&re)[R], const S (&im)[R]) 
     return q;
 }
 
-// fixed-order workgroup sum of NV values (wave butterflies, then waves in order)
+// wave sums with ds_swizzle butterflies inside each half-wave (xor 1 .. 16,
+// no address registers) and the two halves added in lane 0: a fixed order
+template <int PAT>
+__device__ __forceinline__ float swz(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_ds_swizzle(__builtin_bit_cast(int, v), PAT));
+}
+template <int PAT>
+__device__ __forceinline__ double swz(double v) {
+    const int2 h = __builtin_bit_cast(int2, v);
+    return __builtin_bit_cast(double, make_int2(__builtin_amdgcn_ds_swizzle(h.x, PAT),
+                                                __builtin_amdgcn_ds_swizzle(h.y, PAT)));
+}
+__device__ __forceinline__ float lane32(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 32));
+}
+__device__ __forceinline__ double lane32(double v) {
+    const int2 h = __builtin_bit_cast(int2, v);
+    return __builtin_bit_cast(double, make_int2(__builtin_amdgcn_readlane(h.x, 32), __builtin_amdgcn_readlane(h.y, 32)));
+}
+template <typename S>
+__device__ __forceinline__ S wave_sum(S v) {
+    // swizzle bit mode: and_mask 0x1f, xor_mask m << 10
+    v += swz<0x041F>(v);
+    v += swz<0x081F>(v);
+    v += swz<0x101F>(v);
+    v += swz<0x201F>(v);
+    v += swz<0x401F>(v);
+    return v + lane32(v);   // valid in lane 0
+}
+
+// fixed-order workgroup sum of NV values (wave sums, then waves in order)
 template <typename S, int T, int NV>
 __device__ __forceinline__ void block_sum(S (&v)[NV], S* red) {
 #pragma unroll
-    for (int q = 0; q < NV; ++q)
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) v[q] += __shfl_xor(v[q], o, 64);
+    for (int q = 0; q < NV; ++q) v[q] = wave_sum(v[q]);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     __syncthreads();
     if (lane == 0)
@@ -348,13 +376,12 @@ __global__ __launch_bounds__((1 << LOGM) >> LOGR) void toeplitz_run_kernel(
         xs[0] = acc[0];
         xs[1] = acc[1];
     }
-    S msum[5] = {0, 0, 0, 0, 0}, mcmp[5] = {0, 0, 0, 0, 0};
+    // Kahan pairs of the window moments live in LDS (thread 0 only), not in
+    // registers every thread would carry through the transforms
+    __shared__ S kmom[10];
     if (t == 0)
 #pragma unroll
-        for (int m = 0; m < 5; ++m) {
-            msum[m] = mom[(2 * m) * Bp + k];
-            mcmp[m] = mom[(2 * m + 1) * Bp + k];
-        }
+        for (int m = 0; m < 10; ++m) kmom[m] = mom[m * Bp + k];
     for (int64_t st = step0; st < step0 + n_steps; ++st) {
         // the thread index made opaque per step: every address below is then
         // recomputed where it is used instead of being kept live (R of each)
@@ -444,15 +471,12 @@ __global__ __launch_bounds__((1 << LOGM) >> LOGR) void toeplitz_run_kernel(
             const S T2 = S(0.25) * (acc[0] * acc[0] + acc[1] * acc[1]);
             const S v[5] = {T2, T2 * acc[2], T2 * T2, acc[2], acc[2] * acc[2]};
 #pragma unroll
-            for (int m = 0; m < 5; ++m) kahan(msum[m], mcmp[m], v[m]);
+            for (int m = 0; m < 5; ++m) kahan(kmom[2 * m], kmom[2 * m + 1], v[m]);
         }
     }
     if (t == 0)
 #pragma unroll
-        for (int m = 0; m < 5; ++m) {
-            mom[(2 * m) * Bp + k] = msum[m];
-            mom[(2 * m + 1) * Bp + k] = mcmp[m];
-        }
+        for (int m = 0; m < 10; ++m) mom[m * Bp + k] = kmom[m];
 }
 
 // host FFT (FP64, radix 2) of the circulant's first column: its eigenvalues
