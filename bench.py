@@ -133,6 +133,55 @@ def adjoint_cost(twa, steps=2048, reps=1):
             "gradients": grads}
 
 
+def scan_points(n_points=96, seed=0):
+    """The uneven phase-diagram scan: N uniform in {64 .. 4096}, alpha on 12
+    values in [0, 3], w on 8 log-spaced values in [1e-2, 1e2] Gamma (96
+    (alpha, w) pairs, one N each); dt from the step criterion 0.04 / max(Gamma
+    N, lam_max) with lam_max bounded by the largest row sum of Eq. (2)."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    pts = []
+    for a in np.linspace(0.0, 3.0, 12):
+        for w in np.logspace(-2, 2, 8):
+            N = int(rng.integers(64, 4097))
+            i = np.arange(N)
+            rowmax = float(max((w / (1.0 + np.abs(i - r)) ** a).sum() for r in (0, N // 2)))
+            pts.append((N, float(w), float(a), 0.04 / max(N, rowmax), 1000 + len(pts)))
+    return pts[:n_points]
+
+
+def batch_scan(twa, steps):
+    """Batched scan (grouped persistent launches, graph replay, autotuned
+    tiles) against the same 96 points run one by one through the plain FP32
+    path, and one by one through the Toeplitz path; device time of the step
+    loops (pump builds excluded), 512 trajectories, FP32."""
+    import torch
+    pts = scan_points()
+    B = 512
+    t0 = time.time()
+    res = twa.run_batch(pts, B, steps, precision="fp32")
+    torch.cuda.synchronize()
+    batch_wall = time.time() - t0
+    batch_ms = res[0]["kernel_ms"]
+    single_ms = 0.0
+    toep_ms = 0.0
+    for i, (N, w, a, dt, seed) in enumerate(pts):
+        p = twa.build_pump(N, w, a)
+        r = twa.run(p, B, dt, steps, seed=seed, point=i, precision="fp32")
+        single_ms += r.obs["kernel_ms"]
+        p.close()
+        lt = twa.build_pump_toeplitz(N, w, a)
+        t = twa.run(lt, B, dt, steps, seed=seed, point=i, precision="fp32", pump_path="toeplitz")
+        toep_ms += t.obs["kernel_ms"]
+    work = sum(B * N * steps for (N, _, _, _, _) in pts)
+    return {"points": len(pts), "n_traj": B, "steps": steps, "precision": "fp32",
+            "batched_ms": batch_ms, "single_runs_ms": single_ms, "toeplitz_single_runs_ms": toep_ms,
+            "speedup_batched_vs_single": single_ms / batch_ms,
+            "speedup_toeplitz_vs_single": single_ms / toep_ms,
+            "batched_rate": work / (batch_ms * 1e-3), "unit": "trajectory-atom-steps/s",
+            "batch_wall_s_incl_pumps_and_tuning": batch_wall}
+
+
 def toeplitz_rate(twa, N, w, alpha, B, dt, T, dense_value):
     """The same workload through the circulant embedding of Eq. (2) (FFT
     drift and circulant pump noise, equal in law to the dense path), FP32,
@@ -164,6 +213,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-toeplitz", action="store_true")
+    ap.add_argument("--batch-scan", type=int, default=0,
+                    help="also time the 96-point scan for this many steps (batched vs single runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (trajectories would shard "
@@ -242,6 +293,9 @@ def main():
     if not args.no_toeplitz:
         print("[bench] Toeplitz fast path on the same workload (FP32)", file=sys.stderr, flush=True)
         line["toeplitz_path"] = toeplitz_rate(twa, N, w, alpha, B, dt, T, value)
+    if args.batch_scan > 0:
+        print("[bench] batched scan, 96 points, %d steps" % args.batch_scan, file=sys.stderr, flush=True)
+        line["batch_scan"] = batch_scan(twa, args.batch_scan)
     if not args.no_adjoint:
         print("[bench] adjoint cost ratio (N=2000, FP32)", file=sys.stderr, flush=True)
         line["adjoint"] = adjoint_cost(twa)
