@@ -59,6 +59,13 @@ extern "C" {
 #define TWA_PREC_FP32   1   /* FP32 state, FP32 MFMA contraction               */
 #define TWA_PREC_BF16   2   /* FP32 state, BF16 MFMA inputs, FP32 accumulation */
 #define TWA_PREC_FP16   3   /* FP32 state, FP16 MFMA inputs, FP32 accumulation */
+#define TWA_PREC_BF16X3 4   /* FP32 state; each contraction operand split into   */
+                            /* bf16 hi + lo (x = hi + lo + O(2^-17 |x|)) and the  */
+                            /* product formed as Ahi Xhi + Ahi Xlo + Alo Xhi on   */
+                            /* BF16 MFMA with FP32 accumulation (the split scheme */
+                            /* of Henry, Tang and Heinecke 2019): near-FP32       */
+                            /* accuracy at three BF16 contractions.  twa_run only,*/
+                            /* no two-time lags, dense pumps without decay        */
 
 /* tile_config reported when the fused small-N kernel integrated the run */
 #define TWA_TILE_FUSED  99

@@ -23,7 +23,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libtwa.so")
 
 TWA_OK, TWA_EINVAL, TWA_ENOMEM, TWA_EHIP, TWA_ENOTPSD, TWA_EUNSTABLE = 0, -1, -2, -3, -4, -5
-PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "fp16": 3}
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "fp16": 3, "bf16x3": 4}
 INTEGRATORS = {"heun": 0, "sib": 1}
 PUMP_PATHS = {"dense": 0, "toeplitz": 1}
 

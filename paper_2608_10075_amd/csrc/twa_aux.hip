@@ -17,7 +17,9 @@ struct P_ {
 
 static inline unsigned nblocks(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
-// A = [-dt/2 W | -sqrt(dt) F], zero padded to [P][2P]
+// A = [-dt/2 W | -sqrt(dt) F], zero padded to [P][2P]; in the split form
+// [P][6P] = [Wh | Wh | Wl | Fh | Fh | Fl] against operand columns
+// (sh, sl, sh, zh, zl, zh)
 template <int PREC>
 __global__ void build_A_kernel(const double* W, const double* F, int64_t N, int64_t P, double cw,
                                double cf, typename Prec<PREC>::G* A) {
@@ -29,7 +31,16 @@ __global__ void build_A_kernel(const double* W, const double* F, int64_t N, int6
         if (j < N) v = cw * W[i * N + j];
         else if (j >= P && j - P < N) v = cf * F[i * N + (j - P)];
     }
-    A[t] = Prec<PREC>::to_g((typename Prec<PREC>::S)v);
+    if constexpr (Prec<PREC>::SPLIT == 3) {
+        uint16_t hi, lo;
+        bf16_split((float)v, hi, lo);
+        typename Prec<PREC>::G* row = A + i * 6 * P + (j < P ? j : 3 * P + (j - P));
+        row[0].v = hi;
+        row[P].v = hi;
+        row[2 * P].v = lo;
+    } else {
+        A[t] = Prec<PREC>::to_g((typename Prec<PREC>::S)v);
+    }
 }
 
 template <int PREC>
@@ -47,6 +58,7 @@ static int build_A_t(const Geometry& g, const double* W, const double* F, double
         case TWA_PREC_FP32: { constexpr int PR = TWA_PREC_FP32; return CALL; } \
         case TWA_PREC_BF16: { constexpr int PR = TWA_PREC_BF16; return CALL; } \
         case TWA_PREC_FP16: { constexpr int PR = TWA_PREC_FP16; return CALL; } \
+        case TWA_PREC_BF16X3: { constexpr int PR = TWA_PREC_BF16X3; return CALL; } \
     }                                                              \
     set_error("unknown precision");                                \
     return TWA_EINVAL;
@@ -86,8 +98,9 @@ __global__ void init_kernel(int64_t N, int64_t B, int64_t P, int64_t Bp, double 
     s[SP + t] = y;
     s[2 * SP + t] = z;
     norm0[t] = x * x + y * y + z * z;
-    Xop[opcol(k, 0) * 2 * P + i] = Prec<PREC>::to_g(x);
-    Xop[opcol(k, 1) * 2 * P + i] = Prec<PREC>::to_g(y);
+    constexpr int SPL = Prec<PREC>::SPLIT;
+    put_op<PREC>(Xop + opcol(k, 0) * 2 * P * SPL + i, P, x);
+    put_op<PREC>(Xop + opcol(k, 1) * 2 * P * SPL + i, P, y);
 }
 
 template <int PREC>
@@ -152,13 +165,14 @@ __global__ void noise_kernel(int64_t N, int64_t B, int64_t P, int64_t Bp, uint32
         box_muller(w.x, w.y, z0, z1);
         box_muller(w.z, w.w, z2, z3);
         const int64_t i = 2 * m;
-        typename Prec<PREC>::G* cx = Xop + opcol(k, 0) * 2 * P + P;
-        typename Prec<PREC>::G* cy = Xop + opcol(k, 1) * 2 * P + P;
-        cx[i] = Prec<PREC>::to_g(z0);
-        cy[i] = Prec<PREC>::to_g(z1);
+        constexpr int SPL = Prec<PREC>::SPLIT;
+        typename Prec<PREC>::G* cx = Xop + opcol(k, 0) * 2 * P * SPL + P * SPL;
+        typename Prec<PREC>::G* cy = Xop + opcol(k, 1) * 2 * P * SPL + P * SPL;
+        put_op<PREC>(cx + i, P, z0);
+        put_op<PREC>(cy + i, P, z1);
         if (i + 1 < N) {
-            cx[i + 1] = Prec<PREC>::to_g(z2);
-            cy[i + 1] = Prec<PREC>::to_g(z3);
+            put_op<PREC>(cx + i + 1, P, z2);
+            put_op<PREC>(cy + i + 1, P, z3);
         }
         if (m == 0) {
             const U4 v = philox4x32_10(U4{0u, (uint32_t)k, n, TAG_COLLECTIVE | (point << 8)}, k0, k1);

@@ -78,6 +78,7 @@ __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
     u += 0x7FFFu + ((u >> 16) & 1u);
     return (uint16_t)(u >> 16);
 }
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
@@ -87,6 +88,7 @@ struct Prec;
 
 template <>
 struct Prec<TWA_PREC_FP64> {
+    static constexpr int SPLIT = 1;   // operand blocks per value (3: bf16 hi, lo, hi)
     typedef double G;   // contraction operand
     typedef double S;   // state / accumulator
     typedef f64x4 AV;
@@ -104,6 +106,7 @@ struct Prec<TWA_PREC_FP64> {
 
 template <>
 struct Prec<TWA_PREC_FP32> {
+    static constexpr int SPLIT = 1;
     // 16x16 MFMA output: register r of lane l holds row 4 (l/16) + r
     __device__ static __forceinline__ int arow(int m) { return m; }
     typedef float G;
@@ -121,6 +124,7 @@ struct Prec<TWA_PREC_FP32> {
 
 template <>
 struct Prec<TWA_PREC_BF16> {
+    static constexpr int SPLIT = 1;
     // 16x16 MFMA output: register r of lane l holds row 4 (l/16) + r
     __device__ static __forceinline__ int arow(int m) { return m; }
     typedef bf16s G;
@@ -135,6 +139,7 @@ struct Prec<TWA_PREC_BF16> {
 
 template <>
 struct Prec<TWA_PREC_FP16> {
+    static constexpr int SPLIT = 1;
     // 16x16 MFMA output: register r of lane l holds row 4 (l/16) + r
     __device__ static __forceinline__ int arow(int m) { return m; }
     typedef _Float16 G;
@@ -146,5 +151,34 @@ struct Prec<TWA_PREC_FP16> {
                                                    0, 0);
     }
 };
+
+// Split BF16: every operand value x is stored as three K blocks (hi, lo, hi)
+// with hi = bf16(x), lo = bf16(x - hi), and the pump matrix as (hi, hi, lo),
+// so that one BF16 contraction over the tripled K sums Ahi Xhi + Ahi Xlo +
+// Alo Xhi; the dropped Alo Xlo and the rounding of lo are O(2^-17) relative.
+template <>
+struct Prec<TWA_PREC_BF16X3> : Prec<TWA_PREC_BF16> {
+    static constexpr int SPLIT = 3;
+};
+
+// operand hi / lo parts of a value (for the split form)
+__device__ __forceinline__ void bf16_split(float v, uint16_t& hi, uint16_t& lo) {
+    hi = f32_to_bf16_rne(v);
+    lo = f32_to_bf16_rne(v - bf16_to_f32(hi));
+}
+
+// one operand value: p[0], or for the split form (hi, lo, hi) blk elements apart
+template <int PREC>
+__device__ __forceinline__ void put_op(typename Prec<PREC>::G* p, int64_t blk, typename Prec<PREC>::S v) {
+    if constexpr (Prec<PREC>::SPLIT == 3) {
+        uint16_t hi, lo;
+        bf16_split(v, hi, lo);
+        p[0].v = hi;
+        p[blk].v = lo;
+        p[2 * blk].v = hi;
+    } else {
+        p[0] = Prec<PREC>::to_g(v);
+    }
+}
 
 }  // namespace twa

@@ -44,6 +44,7 @@ int pick_tile_cfg(int precision, int64_t N, int64_t n_traj);
 inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 int gemm_elt_bytes(int precision);
 int state_elt_bytes(int precision);
+int operand_split(int precision);   // K blocks per operand value (3 for TWA_PREC_BF16X3)
 
 // ---------------------------------------------------------------------------
 // device buffers and launch geometry of one trajectory ensemble

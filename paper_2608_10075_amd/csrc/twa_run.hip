@@ -24,6 +24,7 @@ int gemm_elt_bytes(int precision) {
     }
 }
 int state_elt_bytes(int precision) { return precision == TWA_PREC_FP64 ? 8 : 4; }
+int operand_split(int precision) { return precision == TWA_PREC_BF16X3 ? 3 : 1; }
 
 int pick_tile_cfg(int precision, int64_t N, int64_t n_traj) {
     if (N <= 48) return 0;
@@ -256,9 +257,10 @@ int alloc_buffers(const Geometry& g, bool tangents, int64_t L, int J, EnsembleBu
     int rc;
 #define TWA_A(ptr, bytes) \
     if ((rc = dalloc((void**)&(ptr), (bytes))) != TWA_OK) return rc;
-    TWA_A(b.A, P * 2 * P * ge)
-    TWA_A(b.Xop, C2 * 2 * P * ge)
-    TWA_A(b.Dop, C2 * P * ge)
+    const size_t spl = (size_t)operand_split(g.precision);   // split form: hi, lo, hi blocks
+    TWA_A(b.A, P * 2 * P * ge * spl)
+    TWA_A(b.Xop, C2 * 2 * P * ge * spl)
+    TWA_A(b.Dop, C2 * P * ge * spl)
     TWA_A(b.s[0], 3 * Bp * P * se)
     TWA_A(b.s[1], 3 * Bp * P * se)
     TWA_A(b.dlt, 3 * Bp * P * se)

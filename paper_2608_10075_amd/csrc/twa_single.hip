@@ -103,8 +103,12 @@ int run_single(const twa_params* p, int64_t n_traj, double dt, int64_t n_steps, 
         set_error("twa_run: the two-time response copies are defined for the Heun integrator (n_lags must be 0)");
         return TWA_EINVAL;
     }
-    if (p->precision < TWA_PREC_FP64 || p->precision > TWA_PREC_FP16) {
+    if (p->precision < TWA_PREC_FP64 || p->precision > TWA_PREC_BF16X3) {
         set_error("twa_run: unknown precision");
+        return TWA_EINVAL;
+    }
+    if (p->precision == TWA_PREC_BF16X3 && (p->n_lags > 0 || (p->pump && p->pump->G))) {
+        set_error("twa_run: the split-BF16 precision runs the forward step without lags or decay matrix");
         return TWA_EINVAL;
     }
     const twa_pump* pump = p->pump;

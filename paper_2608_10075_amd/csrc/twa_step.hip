@@ -134,6 +134,23 @@ __device__ __forceinline__ void stg4(typename Prec<PREC>::G* p, const typename P
 #pragma unroll
     for (int r = 0; r < 4; ++r) p[r] = Prec<PREC>::to_g(v[r]);
 }
+// operand store of a state-like value: one block, or for the split form the
+// (hi, lo, hi) blocks blk elements apart
+template <int PREC>
+__device__ __forceinline__ void stg4s(typename Prec<PREC>::G* p, int64_t blk, const typename Prec<PREC>::S (&v)[4]) {
+    if constexpr (Prec<PREC>::SPLIT == 3) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            uint16_t hi, lo;
+            bf16_split(v[r], hi, lo);
+            p[r].v = hi;
+            p[blk + r].v = lo;
+            p[2 * blk + r].v = hi;
+        }
+    } else {
+        stg4<PREC>(p, v);
+    }
+}
 
 // ---------------------------------------------------------------------------
 // contraction + fused Heun stage
@@ -431,8 +448,8 @@ __device__ __forceinline__ void stage_tile(const GemmArgs<PREC>& a, const int mt
                 }
                 st4(a.Y + off, yx);
                 st4(a.Y + SP + off, yy);
-                stg4<PREC>(a.Dop + opcol(k, 0) * P + i0, dx);
-                stg4<PREC>(a.Dop + opcol(k, 1) * P + i0, dy);
+                stg4s<PREC>(a.Dop + opcol(k, 0) * (Prec<PREC>::SPLIT * P) + i0, P, dx);
+                stg4s<PREC>(a.Dop + opcol(k, 1) * (Prec<PREC>::SPLIT * P) + i0, P, dy);
                 if constexpr (QSNAP) {
                     S qx[4], qy[4];
 #pragma unroll
@@ -461,8 +478,8 @@ __device__ __forceinline__ void stage_tile(const GemmArgs<PREC>& a, const int mt
                 }
                 st4(a.Y + off, yx);
                 st4(a.Y + SP + off, yy);
-                stg4<PREC>(a.Dop + opcol(k, 0) * P + i0, dx);
-                stg4<PREC>(a.Dop + opcol(k, 1) * P + i0, dy);
+                stg4s<PREC>(a.Dop + opcol(k, 0) * (Prec<PREC>::SPLIT * P) + i0, P, dx);
+                stg4s<PREC>(a.Dop + opcol(k, 1) * (Prec<PREC>::SPLIT * P) + i0, P, dy);
             } else if constexpr (KD == KIND_SIB && STAGE == 2) {
                 // corrector: the midpoint rule from s_n with the field at the
                 // midpoint m = s_n + D/2: contraction Y1 + A_left D / 2, sums (S_n + S~)/2
@@ -483,8 +500,8 @@ __device__ __forceinline__ void stage_tile(const GemmArgs<PREC>& a, const int mt
                 st4(a.s_next + off, nx);
                 st4(a.s_next + SP + off, ny);
                 st4(a.s_next + 2 * SP + off, nz);
-                stg4<PREC>(a.Xnext + opcol(k, 0) * a.ldxn + i0, nx);
-                stg4<PREC>(a.Xnext + opcol(k, 1) * a.ldxn + i0, ny);
+                stg4s<PREC>(a.Xnext + opcol(k, 0) * a.ldxn + i0, P, nx);
+                stg4s<PREC>(a.Xnext + opcol(k, 1) * a.ldxn + i0, P, ny);
             } else if constexpr (KD == KIND_PRIMAL && STAGE == 2) {
                 S dx[4], dy[4], dz[4], yx[4], yy[4], nx[4], ny[4], nz[4];
                 ld4(a.Y + off, yx);
@@ -529,8 +546,8 @@ __device__ __forceinline__ void stage_tile(const GemmArgs<PREC>& a, const int mt
                     st4(yo + off, yx);
                     st4(yo + SP + off, yy);
                 }
-                stg4<PREC>(a.Xnext + opcol(k, 0) * a.ldxn + i0, nx);
-                stg4<PREC>(a.Xnext + opcol(k, 1) * a.ldxn + i0, ny);
+                stg4s<PREC>(a.Xnext + opcol(k, 0) * a.ldxn + i0, P, nx);
+                stg4s<PREC>(a.Xnext + opcol(k, 1) * a.ldxn + i0, P, ny);
             } else if constexpr (KD == KIND_TANGENT && STAGE == 1) {
                 const S tSx = sT[kl][0], tSy = sT[kl][1];
                 const S* tc = a.t_cur + cp * a.t_state_copy;
@@ -842,22 +859,34 @@ static int launch_kernel(const GemmArgs<PREC>& a, int64_t P, int64_t C2, int nco
 template <int PREC, int CFG>
 static int dispatch_kind(const GemmArgs<PREC>& a, int stage, int kind, int64_t P, int64_t C2, int ncopy,
                          hipStream_t st) {
-    if (stage == 1) {
-        switch (kind) {
-            case KIND_PRIMAL: return launch_kernel<PREC, CFG, 1, KIND_PRIMAL>(a, P, C2, ncopy, st);
-            case KIND_SIB: return launch_kernel<PREC, CFG, 1, KIND_SIB>(a, P, C2, ncopy, st);
-            case KIND_TANGENT: return launch_kernel<PREC, CFG, 1, KIND_TANGENT>(a, P, C2, ncopy, st);
-            case KIND_STORE: return launch_kernel<PREC, CFG, 1, KIND_STORE>(a, P, C2, ncopy, st);
-            case KIND_PRIMAL | KIND_Q_SNAPSHOT:
-                return launch_kernel<PREC, CFG, 1, KIND_PRIMAL | KIND_Q_SNAPSHOT>(a, P, C2, ncopy, st);
-            case KIND_ADJ1: return launch_kernel<PREC, CFG, 1, KIND_ADJ1>(a, P, C2, ncopy, st);
-        }
+    if constexpr (Prec<PREC>::SPLIT == 3) {
+        // the split form runs the forward step only
+        if (kind == KIND_PRIMAL)
+            return stage == 1 ? launch_kernel<PREC, CFG, 1, KIND_PRIMAL>(a, P, C2, ncopy, st)
+                              : launch_kernel<PREC, CFG, 2, KIND_PRIMAL>(a, P, C2, ncopy, st);
+        if (kind == KIND_SIB)
+            return stage == 1 ? launch_kernel<PREC, CFG, 1, KIND_SIB>(a, P, C2, ncopy, st)
+                              : launch_kernel<PREC, CFG, 2, KIND_SIB>(a, P, C2, ncopy, st);
+        set_error("split BF16: forward primal or semi-implicit steps only");
+        return TWA_EINVAL;
     } else {
-        switch (kind) {
-            case KIND_PRIMAL: return launch_kernel<PREC, CFG, 2, KIND_PRIMAL>(a, P, C2, ncopy, st);
-            case KIND_SIB: return launch_kernel<PREC, CFG, 2, KIND_SIB>(a, P, C2, ncopy, st);
-            case KIND_TANGENT: return launch_kernel<PREC, CFG, 2, KIND_TANGENT>(a, P, C2, ncopy, st);
-            case KIND_ADJ2: return launch_kernel<PREC, CFG, 2, KIND_ADJ2>(a, P, C2, ncopy, st);
+        if (stage == 1) {
+            switch (kind) {
+                case KIND_PRIMAL: return launch_kernel<PREC, CFG, 1, KIND_PRIMAL>(a, P, C2, ncopy, st);
+                case KIND_SIB: return launch_kernel<PREC, CFG, 1, KIND_SIB>(a, P, C2, ncopy, st);
+                case KIND_TANGENT: return launch_kernel<PREC, CFG, 1, KIND_TANGENT>(a, P, C2, ncopy, st);
+                case KIND_STORE: return launch_kernel<PREC, CFG, 1, KIND_STORE>(a, P, C2, ncopy, st);
+                case KIND_PRIMAL | KIND_Q_SNAPSHOT:
+                    return launch_kernel<PREC, CFG, 1, KIND_PRIMAL | KIND_Q_SNAPSHOT>(a, P, C2, ncopy, st);
+                case KIND_ADJ1: return launch_kernel<PREC, CFG, 1, KIND_ADJ1>(a, P, C2, ncopy, st);
+            }
+        } else {
+            switch (kind) {
+                case KIND_PRIMAL: return launch_kernel<PREC, CFG, 2, KIND_PRIMAL>(a, P, C2, ncopy, st);
+                case KIND_SIB: return launch_kernel<PREC, CFG, 2, KIND_SIB>(a, P, C2, ncopy, st);
+                case KIND_TANGENT: return launch_kernel<PREC, CFG, 2, KIND_TANGENT>(a, P, C2, ncopy, st);
+                case KIND_ADJ2: return launch_kernel<PREC, CFG, 2, KIND_ADJ2>(a, P, C2, ncopy, st);
+            }
         }
     }
     set_error("unsupported (stage, kind) combination");
@@ -894,8 +923,9 @@ static GemmArgs<PREC> make_args(const Geometry& g, const EnsembleBuffers& b, con
     typedef typename Prec<PREC>::S S;
     GemmArgs<PREC> a{};
     const int64_t P = g.P, Bp = g.Bp;
+    constexpr int SPL = Prec<PREC>::SPLIT;   // K blocks per value (split form: hi, lo, hi)
     a.A = static_cast<const G*>(b.A);
-    a.lda = 2 * P;
+    a.lda = 2 * P * SPL;
     a.P = P;
     a.Bp = Bp;
     a.nmt = g.nmt;
@@ -919,18 +949,18 @@ static GemmArgs<PREC> make_args(const Geometry& g, const EnsembleBuffers& b, con
     if (!tangent) {
         if (stage == 1) {
             a.X = static_cast<const G*>(b.Xop);
-            a.ldx = 2 * P;
-            a.K = 2 * P;
+            a.ldx = 2 * P * SPL;
+            a.K = 2 * P * SPL;
             a.part_prim = static_cast<const S*>(b.part[0]);
             a.part_out = static_cast<S*>(b.part[1]);
         } else {
             a.X = static_cast<const G*>(b.Dop);
-            a.ldx = P;
-            a.K = P;
+            a.ldx = P * SPL;
+            a.K = P * SPL;
             a.part_prim = static_cast<const S*>(b.part[1]);
             a.part_out = static_cast<S*>(b.part[0]);
             a.Xnext = static_cast<G*>(b.Xop);
-            a.ldxn = 2 * P;
+            a.ldxn = 2 * P * SPL;
         }
     } else {
         a.t_cur = static_cast<const S*>(b.ts[cur]);
@@ -974,6 +1004,8 @@ int launch_gemm(const Geometry& g, const EnsembleBuffers& b, const StepConsts& c
         case TWA_PREC_FP32: return launch_gemm_p<TWA_PREC_FP32>(g, b, c, stage, tangent, cur, store_y2, keep_dlt, st);
         case TWA_PREC_BF16: return launch_gemm_p<TWA_PREC_BF16>(g, b, c, stage, tangent, cur, store_y2, keep_dlt, st);
         case TWA_PREC_FP16: return launch_gemm_p<TWA_PREC_FP16>(g, b, c, stage, tangent, cur, store_y2, keep_dlt, st);
+        case TWA_PREC_BF16X3:
+            return launch_gemm_p<TWA_PREC_BF16X3>(g, b, c, stage, tangent, cur, store_y2, keep_dlt, st);
     }
     set_error("unknown precision");
     return TWA_EINVAL;
