@@ -70,8 +70,13 @@ def traffic_from_profiles(workload: str, precision: str):
     return d.get("bytes_per_launch")
 
 
-def cpu_baseline(N, w, alpha, dt, budget_s=15.0):
-    """The FP64 oracle as it stands, timed on a bounded sample of the workload."""
+def cpu_baseline(N, w, alpha, dt, budget_s=15.0, threads=None):
+    """The FP64 oracle as it stands, timed on a bounded sample of the workload
+    (BLAS threads: all, or limited to ``threads``)."""
+    if threads is not None:
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=threads):
+            return cpu_baseline(N, w, alpha, dt, budget_s)
     import numpy as np
     from oracle import pump as opump, twa as otwa
     try:
@@ -134,20 +139,25 @@ def adjoint_cost(twa, steps=2048, reps=1):
 
 
 def scan_points(n_points=96, seed=0):
-    """The uneven phase-diagram scan: N uniform in {64 .. 4096}, alpha on 12
-    values in [0, 3], w on 8 log-spaced values in [1e-2, 1e2] Gamma (96
-    (alpha, w) pairs, one N each); dt from the step criterion 0.04 / max(Gamma
-    N, lam_max) with lam_max bounded by the largest row sum of Eq. (2)."""
+    """The uneven phase-diagram scan: N_p = default_rng(0).integers(64, 4097,
+    96), (alpha, w) over linspace(0, 3, 12) x logspace(-2, 2, 8) in row-major
+    order, seed = point index; dt from the step criterion 0.04 / max(Gamma N,
+    lam_max) (below the paper's 0.05) with lam_max bounded by the largest row
+    sum of Eq. (2) (the row sums peak at the middle row)."""
     import numpy as np
-    rng = np.random.default_rng(seed)
+    Ns = np.random.default_rng(seed).integers(64, 4097, n_points)
     pts = []
+    q = 0
     for a in np.linspace(0.0, 3.0, 12):
         for w in np.logspace(-2, 2, 8):
-            N = int(rng.integers(64, 4097))
+            if q == n_points:
+                break
+            N = int(Ns[q])
             i = np.arange(N)
-            rowmax = float(max((w / (1.0 + np.abs(i - r)) ** a).sum() for r in (0, N // 2)))
-            pts.append((N, float(w), float(a), 0.04 / max(N, rowmax), 1000 + len(pts)))
-    return pts[:n_points]
+            rowmax = float((w / (1.0 + np.abs(i - N // 2)) ** a).sum())
+            pts.append((N, float(w), float(a), 0.04 / max(N, rowmax), q))
+            q += 1
+    return pts
 
 
 def batch_scan(twa, steps):
@@ -174,7 +184,9 @@ def batch_scan(twa, steps):
         t = twa.run(lt, B, dt, steps, seed=seed, point=i, precision="fp32", pump_path="toeplitz")
         toep_ms += t.obs["kernel_ms"]
     work = sum(B * N * steps for (N, _, _, _, _) in pts)
+    crit = [r["step_criterion"] for r in res]
     return {"points": len(pts), "n_traj": B, "steps": steps, "precision": "fp32",
+            "N_list": [p[0] for p in pts], "step_criterion_min_max": [min(crit), max(crit)],
             "batched_ms": batch_ms, "single_runs_ms": single_ms, "toeplitz_single_runs_ms": toep_ms,
             "speedup_batched_vs_single": single_ms / batch_ms,
             "speedup_toeplitz_vs_single": single_ms / toep_ms,
@@ -302,6 +314,7 @@ def main():
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(N, w, alpha, dt)
+        line["cpu_baseline_single_core"] = cpu_baseline(N, w, alpha, dt, budget_s=8.0, threads=1)
     print(json.dumps(line), flush=True)
 
 
