@@ -51,6 +51,27 @@ def factor(M: np.ndarray) -> np.ndarray:
     return 0.5 * (R + R.T)
 
 
+class Exchange:
+    """Drift matrix with coherent exchange H = sum_{i != j} Omega_ij s+_i s-_j
+    (Omega real symmetric, zero diagonal; the coherent dipole-dipole part of
+    the Green-tensor kernels named in the Perspectives, which prints no
+    equations for it).  Heisenberg's equation for Pauli spins gives
+    d s^x_i = s^z_i (Omega s^y)_i dt, d s^y_i = -s^z_i (Omega s^x)_i dt,
+    d s^z_i = (s^y_i (Omega s^x)_i - s^x_i (Omega s^y)_i) dt, i.e. s_i x b_i
+    with b_i = -(Omega s^x, Omega s^y, 0)_i: in the field of Eq. (S1) it adds
+    +dt (Omega s^y)_i to h^x_i and -dt (Omega s^x)_i to h^y_i."""
+
+    def __init__(self, W: np.ndarray, omega: np.ndarray):
+        self.W = np.asarray(W, dtype=np.float64)
+        self.omega = np.asarray(omega, dtype=np.float64)
+        if self.omega.shape != self.W.shape or np.any(np.diag(self.omega) != 0) or \
+                not np.array_equal(self.omega, self.omega.T):
+            raise ValueError("Omega must be symmetric with a zero diagonal, of the size of W")
+
+    def apply(self, v):
+        return v @ self.W.T
+
+
 def model_pump(W: np.ndarray, G: np.ndarray) -> Pump:
     """Matrices of the correlated-decay step: drift W - G, noise factor
     sqrt(W + G) (eigen-decomposition of W + G, clamped as for the pump)."""

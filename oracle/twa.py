@@ -75,6 +75,8 @@ class RunConfig:
                                            # so any subset of an ensemble can be integrated alone)
     decay: Optional[np.ndarray] = None     # (N, N) symmetric PSD correlated-decay matrix G; replaces
                                            # the collective decay (gamma unused), see oracle.decay
+    exchange: Optional[np.ndarray] = None  # (N, N) symmetric zero-diagonal coherent exchange Omega
+                                           # (oracle.decay.Exchange), Heun and semi-implicit only
     toeplitz: bool = False                 # apply Eq. (2) through its circulant embedding and draw
                                            # the pump noise from it (oracle.toeplitz)
 
@@ -132,6 +134,10 @@ def increment(state, W, gamma, dt, dxi, dchi):
     Sy = y.sum(axis=1)[:, None]
     hx = (0.5 * gamma * Sx - 0.5 * _matvec(W, x)) * dt + dxi[0][:, None] - dchi[0]
     hy = (0.5 * gamma * Sy - 0.5 * _matvec(W, y)) * dt + dxi[1][:, None] - dchi[1]
+    om = getattr(W, "omega", None)
+    if om is not None:   # coherent exchange (oracle.decay.Exchange)
+        hx = hx + dt * (y @ om.T)
+        hy = hy - dt * (x @ om.T)
     return z * hx, z * hy, -(x * hx + y * hy), (hx, hy)
 
 
@@ -140,6 +146,8 @@ def increment_tangent(state, dstate, fields, W, gamma, dt):
     x, y, z = state
     dx, dy, dz = dstate
     hx, hy = fields
+    if getattr(W, "omega", None) is not None:
+        raise NotImplementedError("response copies are defined without coherent exchange")
     dhx = (0.5 * gamma * dx.sum(axis=1)[:, None] - 0.5 * _matvec(W, dx)) * dt
     dhy = (0.5 * gamma * dy.sum(axis=1)[:, None] - 0.5 * _matvec(W, dy)) * dt
     return (dz * hx + z * dhx,
@@ -264,6 +272,10 @@ def run(cfg: RunConfig, pump: Optional[Pump] = None) -> RunResult:
         pump = odecay.model_pump(pump.W, G)
         cfg = replace(cfg, gamma=0.0)    # the matrix replaces the collective terms
     W = pump if cfg.toeplitz else pump.W
+    if cfg.exchange is not None:
+        if cfg.toeplitz or cfg.n_lags > 0:
+            raise NotImplementedError("coherent exchange: dense pump, no two-time response copies")
+        W = odecay.Exchange(W, cfg.exchange)
     B, T = cfg.n_traj, cfg.n_steps
     burn = cfg.resolved_burnin()
     if cfg.init_state is not None:
