@@ -130,20 +130,30 @@ TWA_API int twa_build_pump_dense(int64_t N, const double* W_host, twa_pump** out
  * twa_build_model_dense -- a model handle for correlated decay: the pump W
  * and a correlated-decay matrix G (both host, row-major FP64, N x N,
  * symmetric; G must be PSD and is G_ab of SM Sec. S1 step 6), the general
- * decay matrix the paper's Perspectives name.  With such a handle twa_run
- * integrates Eq. (S1) with the collective terms (1/2) Gamma S^a and xi^a
- * replaced by (1/2) sum_j G_ij s^a_j and a noise of covariance G_ij (params
- * gamma is ignored), and reports the correlated-emission intensity and g2
- * (twa_observables I_gen, g2_gen).  The decay and pump noises are drawn as
- * one Gaussian of covariance (W + G) dt (equal in law to two independent
- * draws): the handle stores the drift matrix W - G (twa_pump_copy_matrix
- * which = 0), the PSD square root of W + G (which = 1) and G (which = 2);
- * twa_pump_info reports the eigenvalue range of W + G.  Not accepted by
- * twa_adjoint, and twa_run rejects it with n_lags > 0.
- * Errors: TWA_EINVAL (bad sizes, non-finite or non-symmetric input),
- *         TWA_ENOTPSD (G or W + G not PSD), TWA_ENOMEM, TWA_EHIP.
+ * decay matrix the paper's Perspectives name, and optionally a coherent
+ * exchange Omega (host, N x N, symmetric, zero diagonal, or NULL): the
+ * Hamiltonian sum_{i != j} Omega_ij sigma+_i sigma-_j of the coherent
+ * dipole-dipole part of Green-tensor kernels the Perspectives mention (the
+ * paper prints no equations for it; by Heisenberg's equation it adds
+ * +dt (Omega s^y)_i to h^x_i and -dt (Omega s^x)_i to h^y_i in Eq. (S1)).
+ * With such a handle twa_run integrates Eq. (S1) with the collective terms
+ * (1/2) Gamma S^a and xi^a replaced by (1/2) sum_j G_ij s^a_j and a noise of
+ * covariance G_ij (params gamma is ignored), and reports the
+ * correlated-emission intensity and g2 (twa_observables I_gen, g2_gen).  The
+ * decay and pump noises are drawn as one Gaussian of covariance (W + G) dt
+ * (equal in law to two independent draws): the handle stores the drift
+ * matrix W - G (twa_pump_copy_matrix which = 0), the PSD square root of
+ * W + G (which = 1), G (which = 2) and Omega (which = 3); twa_pump_info
+ * reports the eigenvalue range of W + G.  With Omega the contraction operand
+ * gains a third K block (s^y, -s^x) and the corrector a second one.  Not
+ * accepted by twa_adjoint; twa_run rejects it with n_lags > 0 or the split
+ * precision.
+ * Errors: TWA_EINVAL (bad sizes, non-finite or non-symmetric input, a nonzero
+ *         diagonal of Omega), TWA_ENOTPSD (G or W + G not PSD), TWA_ENOMEM,
+ *         TWA_EHIP.
  */
-TWA_API int twa_build_model_dense(int64_t N, const double* W_host, const double* G_host, twa_pump** out);
+TWA_API int twa_build_model_dense(int64_t N, const double* W_host, const double* G_host, const double* Om_host,
+                                  twa_pump** out);
 
 /*
  * twa_build_pump_toeplitz -- a light handle of Eq. (2) for the Toeplitz fast
@@ -169,8 +179,8 @@ TWA_API int twa_pump_info(const twa_pump* p, int64_t* N, double* lam_min, double
 
 /*
  * twa_pump_copy_matrix -- copies W (which = 0), F (which = 1) or, for a model
- * handle, the decay matrix G (which = 2) into a host row-major N x N FP64
- * buffer.  Errors: TWA_EINVAL, TWA_EHIP.
+ * handle, the decay matrix G (which = 2) or the exchange Omega (which = 3)
+ * into a host row-major N x N FP64 buffer.  Errors: TWA_EINVAL, TWA_EHIP.
  */
 TWA_API int twa_pump_copy_matrix(const twa_pump* p, int which, double* out_host);
 

@@ -97,7 +97,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.twa_build_pump.argtypes = [C.c_int64, C.c_double, C.c_double, C.POINTER(P)]
     lib.twa_build_pump_dense.argtypes = [C.c_int64, C.POINTER(C.c_double), C.POINTER(P)]
     lib.twa_build_pump_toeplitz.argtypes = [C.c_int64, C.c_double, C.c_double, C.POINTER(P)]
-    lib.twa_build_model_dense.argtypes = [C.c_int64, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(P)]
+    lib.twa_build_model_dense.argtypes = [C.c_int64, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                          C.POINTER(C.c_double), C.POINTER(P)]
     lib.twa_pump_free.argtypes = [P]
     lib.twa_pump_free.restype = None
     lib.twa_pump_info.argtypes = [P, C.POINTER(C.c_int64), C.POINTER(C.c_double), C.POINTER(C.c_double)]
@@ -159,7 +160,8 @@ class Pump:
     With ``decay`` (and ``dense``): a model handle for correlated decay."""
 
     def __init__(self, N: int, w: float = None, alpha: float = None, dense: Optional[np.ndarray] = None,
-                 decay: Optional[np.ndarray] = None, toeplitz_only: bool = False):
+                 decay: Optional[np.ndarray] = None, toeplitz_only: bool = False,
+                 exchange: Optional[np.ndarray] = None):
         h = C.c_void_p()
         self.has_decay = decay is not None
         if toeplitz_only:
@@ -168,8 +170,12 @@ class Pump:
             W = np.ascontiguousarray(dense, dtype=np.float64)
             G = np.ascontiguousarray(decay, dtype=np.float64)
             assert W.shape == (N, N) and G.shape == (N, N)
+            O = None if exchange is None else np.ascontiguousarray(exchange, dtype=np.float64)
+            assert O is None or O.shape == (N, N)
             _check(_lib.twa_build_model_dense(int(N), W.ctypes.data_as(C.POINTER(C.c_double)),
-                                              G.ctypes.data_as(C.POINTER(C.c_double)), C.byref(h)))
+                                              G.ctypes.data_as(C.POINTER(C.c_double)),
+                                              None if O is None else O.ctypes.data_as(C.POINTER(C.c_double)),
+                                              C.byref(h)))
         elif dense is not None:
             W = np.ascontiguousarray(dense, dtype=np.float64)
             _check(_lib.twa_build_pump_dense(int(N), W.ctypes.data_as(C.POINTER(C.c_double)), C.byref(h)))
@@ -191,7 +197,7 @@ class Pump:
         """W (for a model handle: the drift matrix W - G), F (the noise factor)
         or G (model handles: the decay matrix)."""
         out = np.empty((self.N, self.N))
-        _check(_lib.twa_pump_copy_matrix(self._h, {"W": 0, "F": 1, "G": 2}[which],
+        _check(_lib.twa_pump_copy_matrix(self._h, {"W": 0, "F": 1, "G": 2, "Omega": 3}[which],
                                          out.ctypes.data_as(C.POINTER(C.c_double))))
         return out
 
@@ -216,10 +222,11 @@ def build_pump_toeplitz(N: int, w: float, alpha: float) -> Pump:
     return Pump(N, w, alpha, toeplitz_only=True)
 
 
-def build_model(W: np.ndarray, decay: np.ndarray) -> Pump:
-    """twa_build_model_dense: pump matrix W and correlated-decay matrix G."""
+def build_model(W: np.ndarray, decay: np.ndarray, exchange: Optional[np.ndarray] = None) -> Pump:
+    """twa_build_model_dense: pump matrix W, correlated-decay matrix G and an
+    optional coherent exchange Omega (symmetric, zero diagonal)."""
     W = np.asarray(W, dtype=np.float64)
-    return Pump(W.shape[0], dense=W, decay=decay)
+    return Pump(W.shape[0], dense=W, decay=decay, exchange=exchange)
 
 
 @dataclass

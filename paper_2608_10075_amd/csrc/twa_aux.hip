@@ -67,12 +67,55 @@ int launch_build_A(const Geometry& g, const double* W, const double* F, double d
     TWA_DISPATCH(g.precision, (build_A_t<PR>(g, W, F, dt, A, st)))
 }
 
+// coherent exchange: A = [-dt/2 W | -sqrt(dt) F | dt Omega] against operand
+// columns (s, zeta, s_perp), and the corrector's A2 = [-dt/2 W | dt Omega]
+// against (D, D_perp), s_perp = (s^y, -s^x) for the (x, y) columns: the field
+// of Eq. (S1) gains +dt (Omega s^y) in h^x and -dt (Omega s^x) in h^y
+template <int PREC>
+__global__ void build_A_coh_kernel(const double* W, const double* F, const double* Om, int64_t N, int64_t P,
+                                   double cw, double cf, double co, typename Prec<PREC>::G* A,
+                                   typename Prec<PREC>::G* A2) {
+    typedef typename Prec<PREC>::S S;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= P * 3 * P) return;
+    const int64_t i = t / (3 * P), j = t % (3 * P);
+    const int64_t blk = j / P, jj = j % P;
+    double v = 0.0;
+    if (i < N && jj < N) {
+        const double m = blk == 0 ? W[i * N + jj] : blk == 1 ? F[i * N + jj] : Om[i * N + jj];
+        v = (blk == 0 ? cw : blk == 1 ? cf : co) * m;
+    }
+    A[t] = Prec<PREC>::to_g((S)v);
+    if (blk != 1) A2[i * 2 * P + (blk == 0 ? jj : P + jj)] = Prec<PREC>::to_g((S)v);
+}
+
+template <int PREC>
+static int build_A_coh_t(const Geometry& g, const double* W, const double* F, const double* Om, double dt, void* A,
+                         void* A2, hipStream_t st) {
+    if constexpr (Prec<PREC>::SPLIT != 1) {
+        set_error("coherent exchange: not with the split precision");
+        return TWA_EINVAL;
+    } else {
+        const int64_t n = g.P * 3 * g.P;
+        hipLaunchKernelGGL(build_A_coh_kernel<PREC>, dim3(nblocks(n, 256)), dim3(256), 0, st, W, F, Om, g.N, g.P,
+                           -0.5 * dt, -sqrt(dt), dt, static_cast<typename Prec<PREC>::G*>(A),
+                           static_cast<typename Prec<PREC>::G*>(A2));
+        TWA_HIP_CHECK(hipGetLastError());
+        return TWA_OK;
+    }
+}
+
+int launch_build_A_coh(const Geometry& g, const double* W, const double* F, const double* Om, double dt, void* A,
+                       void* A2, hipStream_t st) {
+    TWA_DISPATCH(g.precision, (build_A_coh_t<PR>(g, W, F, Om, dt, A, A2, st)))
+}
+
 // ---------------------------------------------------------------------------
 // discrete initial sampling: s^{x,y} = +-1 from Philox bits, s^z = s0z
 template <int PREC>
 __global__ void init_kernel(int64_t N, int64_t B, int64_t P, int64_t Bp, double s0z, uint32_t k0, uint32_t k1,
                             uint32_t point, const double* init, typename Prec<PREC>::S* s,
-                            typename Prec<PREC>::S* norm0, typename Prec<PREC>::G* Xop) {
+                            typename Prec<PREC>::S* norm0, typename Prec<PREC>::G* Xop, int coh) {
     typedef typename Prec<PREC>::S S;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= Bp * P) return;
@@ -99,8 +142,13 @@ __global__ void init_kernel(int64_t N, int64_t B, int64_t P, int64_t Bp, double 
     s[2 * SP + t] = z;
     norm0[t] = x * x + y * y + z * z;
     constexpr int SPL = Prec<PREC>::SPLIT;
-    put_op<PREC>(Xop + opcol(k, 0) * 2 * P * SPL + i, P, x);
-    put_op<PREC>(Xop + opcol(k, 1) * 2 * P * SPL + i, P, y);
+    const int64_t ld = (2 + coh) * P * SPL;   // operand column length
+    put_op<PREC>(Xop + opcol(k, 0) * ld + i, P, x);
+    put_op<PREC>(Xop + opcol(k, 1) * ld + i, P, y);
+    if (coh) {   // s_perp block: (s^y, -s^x)
+        Xop[opcol(k, 0) * ld + 2 * P + i] = Prec<PREC>::to_g(y);
+        Xop[opcol(k, 1) * ld + 2 * P + i] = Prec<PREC>::to_g(-x);
+    }
 }
 
 template <int PREC>
@@ -111,7 +159,7 @@ static int init_t(const Geometry& g, const EnsembleBuffers& b, const StepConsts&
     const int64_t n = g.Bp * g.P;
     hipLaunchKernelGGL(init_kernel<PREC>, dim3(nblocks(n, 256)), dim3(256), 0, st, g.N, g.B, g.P, g.Bp, c.s0z,
                        c.key0, c.key1, (uint32_t)c.point, init, static_cast<S*>(b.s[0]), static_cast<S*>(b.norm0),
-                       static_cast<G*>(b.Xop));
+                       static_cast<G*>(b.Xop), g.coh);
     TWA_HIP_CHECK(hipGetLastError());
     return TWA_OK;
 }
@@ -152,7 +200,7 @@ int launch_reduce_state(const Geometry& g, const void* s, void* part, hipStream_
 template <int PREC>
 __global__ void noise_kernel(int64_t N, int64_t B, int64_t P, int64_t Bp, uint32_t k0, uint32_t k1,
                              uint32_t point, const int64_t* step, typename Prec<PREC>::G* Xop,
-                             typename Prec<PREC>::S* g) {
+                             typename Prec<PREC>::S* g, int64_t ldop) {
     typedef typename Prec<PREC>::S S;
     // grid: x over Philox slots (pairs of spins), y over trajectories (strided)
     const int64_t nslot = (N + 1) / 2;
@@ -166,8 +214,8 @@ __global__ void noise_kernel(int64_t N, int64_t B, int64_t P, int64_t Bp, uint32
         box_muller(w.z, w.w, z2, z3);
         const int64_t i = 2 * m;
         constexpr int SPL = Prec<PREC>::SPLIT;
-        typename Prec<PREC>::G* cx = Xop + opcol(k, 0) * 2 * P * SPL + P * SPL;
-        typename Prec<PREC>::G* cy = Xop + opcol(k, 1) * 2 * P * SPL + P * SPL;
+        typename Prec<PREC>::G* cx = Xop + opcol(k, 0) * ldop + P * SPL;
+        typename Prec<PREC>::G* cy = Xop + opcol(k, 1) * ldop + P * SPL;
         put_op<PREC>(cx + i, P, z0);
         put_op<PREC>(cy + i, P, z1);
         if (i + 1 < N) {
@@ -191,7 +239,8 @@ static int noise_t(const Geometry& g, const EnsembleBuffers& b, const StepConsts
                        dim3(256), 0, st, g.N, g.B, g.P,
                        g.Bp, c.key0,
                        c.key1, (uint32_t)c.point, (const int64_t*)b.step,
-                       static_cast<typename Prec<PREC>::G*>(b.Xop), static_cast<typename Prec<PREC>::S*>(b.g));
+                       static_cast<typename Prec<PREC>::G*>(b.Xop), static_cast<typename Prec<PREC>::S*>(b.g),
+                       (int64_t)(2 + g.coh) * g.P * Prec<PREC>::SPLIT);
     TWA_HIP_CHECK(hipGetLastError());
     return TWA_OK;
 }

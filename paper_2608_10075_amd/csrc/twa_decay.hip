@@ -123,7 +123,7 @@ int observe_t(const Geometry& g, const EnsembleBuffers& b, int cur, hipStream_t 
     c.A = b.AG;
     c.lda = g.P;
     c.X = b.Xop;
-    c.ldx = 2 * g.P;
+    c.ldx = (2 + g.coh) * g.P;   // the state block leads every operand column
     c.K = g.P;
     c.Sout = b.GX;
     c.store_sign = 1.0;

@@ -52,6 +52,7 @@ struct Geometry {
     int precision;
     int cfg;
     int integrator = TWA_INT_HEUN;
+    int coh = 0;         // coherent exchange: operand columns (s | zeta | s_perp), corrector [D | D_perp]
     int64_t N, B;        // atoms, trajectories
     int64_t P, Bp;       // padded
     int64_t nmt;         // P / MT
@@ -61,8 +62,11 @@ struct Geometry {
 
 struct EnsembleBuffers {
     void* A = nullptr;          // GT [P][2P]  = [-dt/2 W | -sqrt(dt) F]
-    void* Xop = nullptr;        // GT [C2][2P] rows: (s^a | zeta^a) of one column
-    void* Dop = nullptr;        // GT [C2][P]  predictor increments
+                                //    coherent exchange: [P][3P] = [-dt/2 W | -sqrt(dt) F | dt Omega]
+    void* A2 = nullptr;         // GT [P][2P]  coherent exchange only: [-dt/2 W | dt Omega] (corrector)
+    void* Xop = nullptr;        // GT [C2][2P] rows: (s^a | zeta^a) of one column; coherent exchange
+                                //    [C2][3P] with s_perp = (s^y, -s^x) for the (x, y) columns
+    void* Dop = nullptr;        // GT [C2][P]  predictor increments (coherent exchange [C2][2P]: D, D_perp)
     void* s[2] = {nullptr, nullptr};   // ST [3][Bp][P] ping-pong state
     void* dlt = nullptr;        // ST [3][Bp][P] predictor increment (kept only where response copies need it)
     void* Sn = nullptr;         // ST [2][Bp] collective sums S^x, S^y of the step's input state
@@ -153,6 +157,8 @@ void grouped_free(GroupedPlan& pl);
 
 // kernel launchers (twa_step.hip, twa_aux.hip)
 int launch_build_A(const Geometry& g, const double* W, const double* F, double dt, void* A, hipStream_t st);
+int launch_build_A_coh(const Geometry& g, const double* W, const double* F, const double* Om, double dt, void* A,
+                       void* A2, hipStream_t st);
 int launch_init_state(const Geometry& g, const EnsembleBuffers& b, const StepConsts& c,
                       const double* init_dev, hipStream_t st);
 int launch_reduce_state(const Geometry& g, const void* s, void* part, hipStream_t st);
@@ -205,5 +211,6 @@ struct twa_pump {
     double* lam = nullptr;   // host eigenvalues ascending [N]
     double* G = nullptr;     // device FP64 [N][N] correlated-decay matrix (model handles only); then
                              // W holds the drift matrix W - G and F, V, lam belong to W + G
+    double* Om = nullptr;    // device FP64 [N][N] coherent exchange Omega (model handles, optional)
     int device = 0;
 };

@@ -138,6 +138,7 @@ done:
 
 static void pump_release(twa_pump* p) {
     if (!p) return;
+    hipFree(p->Om);
     hipFree(p->G);
     hipFree(p->W);
     hipFree(p->F);
@@ -286,16 +287,24 @@ TWA_API int twa_build_pump_dense(int64_t N, const double* W_host, twa_pump** out
     return TWA_OK;
 }
 
-TWA_API int twa_build_model_dense(int64_t N, const double* W_host, const double* G_host, twa_pump** out) {
+TWA_API int twa_build_model_dense(int64_t N, const double* W_host, const double* G_host, const double* Om_host,
+                                  twa_pump** out) {
     using namespace twa;
     if (!out || N < 1 || !W_host || !G_host) {
         set_error("twa_build_model_dense: need N >= 1, two matrices and an output pointer");
         return TWA_EINVAL;
     }
-    if (!symmetric_finite(N, W_host) || !symmetric_finite(N, G_host)) {
+    if (!symmetric_finite(N, W_host) || !symmetric_finite(N, G_host) ||
+        (Om_host && !symmetric_finite(N, Om_host))) {
         set_error("twa_build_model_dense: matrices must be finite and symmetric");
         return TWA_EINVAL;
     }
+    if (Om_host)
+        for (int64_t i = 0; i < N; ++i)
+            if (Om_host[i * N + i] != 0.0) {
+                set_error("twa_build_model_dense: the exchange matrix must have a zero diagonal");
+                return TWA_EINVAL;
+            }
     *out = nullptr;
     const size_t bytes = (size_t)N * N * sizeof(double);
     const int64_t n2 = N * N;
@@ -354,6 +363,15 @@ TWA_API int twa_build_model_dense(int64_t N, const double* W_host, const double*
         set_error("twa_build_model_dense: factorisation of W + G failed");
     }
     hipFree(Wd);
+    if (rc == TWA_OK && Om_host) {
+        if (hipMalloc(&p->Om, bytes) != hipSuccess) {
+            set_error("twa_build_model_dense: device allocation failed");
+            rc = TWA_ENOMEM;
+        } else if (hipMemcpy(p->Om, Om_host, bytes, hipMemcpyHostToDevice) != hipSuccess) {
+            set_error("twa_build_model_dense: hipMemcpy failed");
+            rc = TWA_EHIP;
+        }
+    }
     if (rc) {
         pump_release(p);
         return rc;
@@ -395,11 +413,11 @@ TWA_API int twa_pump_info(const twa_pump* p, int64_t* N, double* lam_min, double
 }
 
 TWA_API int twa_pump_copy_matrix(const twa_pump* p, int which, double* out_host) {
-    if (!p || !out_host || which < 0 || which > 2 || (which == 2 && !p->G)) {
-        twa::set_error("twa_pump_copy_matrix: bad arguments (which = 2 needs a model handle)");
+    if (!p || !out_host || which < 0 || which > 3 || (which == 2 && !p->G) || (which == 3 && !p->Om)) {
+        twa::set_error("twa_pump_copy_matrix: bad arguments (which = 2, 3 need a model handle with G, Omega)");
         return TWA_EINVAL;
     }
-    const double* src = which == 0 ? p->W : which == 1 ? p->F : p->G;
+    const double* src = which == 0 ? p->W : which == 1 ? p->F : which == 2 ? p->G : p->Om;
     if (!src) {
         twa::set_error("twa_pump_copy_matrix: the handle holds no dense matrices (Toeplitz handle)");
         return TWA_EINVAL;

@@ -232,7 +232,7 @@ void free_buffers(EnsembleBuffers& b) {
     void* ptrs[] = {b.A,      b.Xop,    b.Dop,  b.s[0], b.s[1],    b.dlt,     b.Y,      b.part[0],
                     b.part[1], b.g,     b.norm0, b.mom, b.tXop,    b.tDop,    b.ts[0],  b.ts[1],
                     b.tdlt,   b.tY,     b.tpart[0], b.tpart[1], b.sm0, b.lag, b.step, b.diag, b.Sn,
-                    b.AG,     b.AGG,    b.Zop,  b.GX,   b.UZ,      b.dg,      b.gmom};
+                    b.AG,     b.AGG,    b.Zop,  b.GX,   b.UZ,      b.dg,      b.gmom,  b.A2};
     for (void* q : ptrs) hipFree(q);
     b = EnsembleBuffers();
 }
@@ -258,9 +258,13 @@ int alloc_buffers(const Geometry& g, bool tangents, int64_t L, int J, EnsembleBu
 #define TWA_A(ptr, bytes) \
     if ((rc = dalloc((void**)&(ptr), (bytes))) != TWA_OK) return rc;
     const size_t spl = (size_t)operand_split(g.precision);   // split form: hi, lo, hi blocks
-    TWA_A(b.A, P * 2 * P * ge * spl)
-    TWA_A(b.Xop, C2 * 2 * P * ge * spl)
-    TWA_A(b.Dop, C2 * P * ge * spl)
+    const size_t ck = g.coh ? 1 : 0;                          // coherent exchange: one more K block
+    TWA_A(b.A, P * (2 + ck) * P * ge * spl)
+    TWA_A(b.Xop, C2 * (2 + ck) * P * ge * spl)
+    TWA_A(b.Dop, C2 * (1 + ck) * P * ge * spl)
+    if (ck) {
+        TWA_A(b.A2, P * 2 * P * ge)
+    }
     TWA_A(b.s[0], 3 * Bp * P * se)
     TWA_A(b.s[1], 3 * Bp * P * se)
     TWA_A(b.dlt, 3 * Bp * P * se)

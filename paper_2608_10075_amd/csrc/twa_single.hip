@@ -134,6 +134,7 @@ int run_single(const twa_params* p, int64_t n_traj, double dt, int64_t n_steps, 
     }
     Geometry g = make_geometry(p->precision, cfg, N, B);
     g.integrator = p->integrator;
+    g.coh = pump->Om ? 1 : 0;
     if (decay) {
         // the packed s^z contraction covers Bp / 2 column pairs
         g.Bp = round_up(B, tile_cfg(cfg).nt);
@@ -200,6 +201,8 @@ int run_single(const twa_params* p, int64_t n_traj, double dt, int64_t n_steps, 
     TWA_TRY(alloc_buffers(g, tangents, L, J, b));
     if (toep)
         TWA_TRY(toeplitz_tables(g, pump->w, pump->alpha, dt, &toep_tw, &toep_spec));
+    else if (g.coh)
+        TWA_TRY(launch_build_A_coh(g, pump->W, pump->F, pump->Om, dt, b.A, b.A2, st));
     else
         TWA_TRY(launch_build_A(g, pump->W, pump->F, dt, b.A, st));
     if (decay) {

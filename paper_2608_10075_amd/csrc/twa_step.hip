@@ -46,6 +46,8 @@ struct GemmArgs {
     S* dlt;
     S* Y;
     G* Dop;             // stage 1 writes
+    int64_t ldd;        // Dop column length (P; SPLIT P in the split form; 2P with coherent exchange)
+    int coh;            // coherent exchange: also write the perpendicular blocks (s^y, -s^x) / (D^y, -D^x)
     G* Xnext;           // stage 2 writes (s-part, ld 2P for primal, P for tangents)
     int64_t ldxn;
     const S* part_prim; // primal partial sums read by the epilogue
@@ -134,6 +136,18 @@ __device__ __forceinline__ void stg4(typename Prec<PREC>::G* p, const typename P
 #pragma unroll
     for (int r = 0; r < 4; ++r) p[r] = Prec<PREC>::to_g(v[r]);
 }
+// coherent exchange: the perpendicular block at row offset off of the x and y
+// columns holds (v^y, -v^x)
+template <int PREC>
+__device__ __forceinline__ void stg4perp(typename Prec<PREC>::G* cx, typename Prec<PREC>::G* cy,
+                                         const typename Prec<PREC>::S (&vx)[4], const typename Prec<PREC>::S (&vy)[4]) {
+    typename Prec<PREC>::S m[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) m[r] = -vx[r];
+    stg4<PREC>(cx, vy);
+    stg4<PREC>(cy, m);
+}
+
 // operand store of a state-like value: one block, or for the split form the
 // (hi, lo, hi) blocks blk elements apart
 template <int PREC>
@@ -448,8 +462,9 @@ __device__ __forceinline__ void stage_tile(const GemmArgs<PREC>& a, const int mt
                 }
                 st4(a.Y + off, yx);
                 st4(a.Y + SP + off, yy);
-                stg4s<PREC>(a.Dop + opcol(k, 0) * (Prec<PREC>::SPLIT * P) + i0, P, dx);
-                stg4s<PREC>(a.Dop + opcol(k, 1) * (Prec<PREC>::SPLIT * P) + i0, P, dy);
+                stg4s<PREC>(a.Dop + opcol(k, 0) * a.ldd + i0, P, dx);
+                stg4s<PREC>(a.Dop + opcol(k, 1) * a.ldd + i0, P, dy);
+                if (a.coh) stg4perp<PREC>(a.Dop + opcol(k, 0) * a.ldd + P + i0, a.Dop + opcol(k, 1) * a.ldd + P + i0, dx, dy);
                 if constexpr (QSNAP) {
                     S qx[4], qy[4];
 #pragma unroll
@@ -478,8 +493,9 @@ __device__ __forceinline__ void stage_tile(const GemmArgs<PREC>& a, const int mt
                 }
                 st4(a.Y + off, yx);
                 st4(a.Y + SP + off, yy);
-                stg4s<PREC>(a.Dop + opcol(k, 0) * (Prec<PREC>::SPLIT * P) + i0, P, dx);
-                stg4s<PREC>(a.Dop + opcol(k, 1) * (Prec<PREC>::SPLIT * P) + i0, P, dy);
+                stg4s<PREC>(a.Dop + opcol(k, 0) * a.ldd + i0, P, dx);
+                stg4s<PREC>(a.Dop + opcol(k, 1) * a.ldd + i0, P, dy);
+                if (a.coh) stg4perp<PREC>(a.Dop + opcol(k, 0) * a.ldd + P + i0, a.Dop + opcol(k, 1) * a.ldd + P + i0, dx, dy);
             } else if constexpr (KD == KIND_SIB && STAGE == 2) {
                 // corrector: the midpoint rule from s_n with the field at the
                 // midpoint m = s_n + D/2: contraction Y1 + A_left D / 2, sums (S_n + S~)/2
@@ -502,6 +518,9 @@ __device__ __forceinline__ void stage_tile(const GemmArgs<PREC>& a, const int mt
                 st4(a.s_next + 2 * SP + off, nz);
                 stg4s<PREC>(a.Xnext + opcol(k, 0) * a.ldxn + i0, P, nx);
                 stg4s<PREC>(a.Xnext + opcol(k, 1) * a.ldxn + i0, P, ny);
+                if (a.coh)
+                    stg4perp<PREC>(a.Xnext + opcol(k, 0) * a.ldxn + 2 * P + i0,
+                                   a.Xnext + opcol(k, 1) * a.ldxn + 2 * P + i0, nx, ny);
             } else if constexpr (KD == KIND_PRIMAL && STAGE == 2) {
                 S dx[4], dy[4], dz[4], yx[4], yy[4], nx[4], ny[4], nz[4];
                 ld4(a.Y + off, yx);
@@ -548,6 +567,9 @@ __device__ __forceinline__ void stage_tile(const GemmArgs<PREC>& a, const int mt
                 }
                 stg4s<PREC>(a.Xnext + opcol(k, 0) * a.ldxn + i0, P, nx);
                 stg4s<PREC>(a.Xnext + opcol(k, 1) * a.ldxn + i0, P, ny);
+                if (a.coh)
+                    stg4perp<PREC>(a.Xnext + opcol(k, 0) * a.ldxn + 2 * P + i0,
+                                   a.Xnext + opcol(k, 1) * a.ldxn + 2 * P + i0, nx, ny);
             } else if constexpr (KD == KIND_TANGENT && STAGE == 1) {
                 const S tSx = sT[kl][0], tSy = sT[kl][1];
                 const S* tc = a.t_cur + cp * a.t_state_copy;
@@ -924,8 +946,11 @@ static GemmArgs<PREC> make_args(const Geometry& g, const EnsembleBuffers& b, con
     GemmArgs<PREC> a{};
     const int64_t P = g.P, Bp = g.Bp;
     constexpr int SPL = Prec<PREC>::SPLIT;   // K blocks per value (split form: hi, lo, hi)
+    const int64_t CK = g.coh ? 1 : 0;         // coherent exchange: one more K block (s_perp, D_perp)
     a.A = static_cast<const G*>(b.A);
-    a.lda = 2 * P * SPL;
+    a.lda = (2 + CK) * P * SPL;
+    a.ldd = (1 + CK) * P * SPL;
+    a.coh = g.coh;
     a.P = P;
     a.Bp = Bp;
     a.nmt = g.nmt;
@@ -949,18 +974,22 @@ static GemmArgs<PREC> make_args(const Geometry& g, const EnsembleBuffers& b, con
     if (!tangent) {
         if (stage == 1) {
             a.X = static_cast<const G*>(b.Xop);
-            a.ldx = 2 * P * SPL;
-            a.K = 2 * P * SPL;
+            a.ldx = (2 + CK) * P * SPL;
+            a.K = (2 + CK) * P * SPL;
             a.part_prim = static_cast<const S*>(b.part[0]);
             a.part_out = static_cast<S*>(b.part[1]);
         } else {
+            if (CK) {   // corrector: [-dt/2 W | dt Omega] against (D, D_perp)
+                a.A = static_cast<const G*>(b.A2);
+                a.lda = 2 * P;
+            }
             a.X = static_cast<const G*>(b.Dop);
-            a.ldx = P * SPL;
-            a.K = P * SPL;
+            a.ldx = (1 + CK) * P * SPL;
+            a.K = (1 + CK) * P * SPL;
             a.part_prim = static_cast<const S*>(b.part[1]);
             a.part_out = static_cast<S*>(b.part[0]);
             a.Xnext = static_cast<G*>(b.Xop);
-            a.ldxn = 2 * P * SPL;
+            a.ldxn = (2 + CK) * P * SPL;
         }
     } else {
         a.t_cur = static_cast<const S*>(b.ts[cur]);
@@ -1036,6 +1065,8 @@ static int launch_call_p(const Geometry& g, const GemmCall& c, hipStream_t st) {
     a.Y = static_cast<S*>(c.Y);
     a.Y2out = static_cast<S*>(c.Y2out);
     a.Dop = static_cast<G*>(c.Dop);
+    a.ldd = g.P;
+    a.coh = 0;
     a.Xnext = static_cast<G*>(c.Xnext);
     a.ldxn = c.ldxn;
     a.part_prim = static_cast<const S*>(c.part_prim);
