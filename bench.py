@@ -194,6 +194,65 @@ def batch_scan(twa, steps):
             "batch_wall_s_incl_pumps_and_tuning": batch_wall}
 
 
+def sib_rate(twa, pump, B, dt, prec, steps=400):
+    """Device time per step of the semi-implicit midpoint scheme against Heun
+    on the headline pump (same three operand sweeps per step)."""
+    out = {}
+    for integ in ("heun", "sib"):
+        twa.run(pump, B, dt, 32, seed=0, precision=prec, integrator=integ)
+        r = twa.run(pump, B, dt, steps, seed=0, precision=prec, integrator=integ)
+        out[integ + "_ms_per_step"] = r.obs["kernel_ms"] / steps
+        out[integ + "_max_norm_dev"] = r.obs["max_norm_dev"]
+    out["steps"] = steps
+    out["precision"] = prec
+    return out
+
+
+def threshold_vs_scan(twa, N=2000, alpha=1.0, B=2048, dt=1e-4, T=2048):
+    """Locating a threshold by Newton steps with adjoint gradients against
+    forward-only searches, at fixed noise: <S+S->/N = target on a bracket
+    found by a coarse scan (target 1, the paper's criterion, when the scan
+    crosses it), FP32, tolerance 1e-6 relative in w."""
+    import numpy as np
+    import torch
+    burn = T // 2
+    grid = np.geomspace(0.5, 64.0, 8)
+    vals, t_fwd = [], []
+    for w in grid:
+        p = twa.build_pump(N, float(w), alpha)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        r = twa.run(p, B, dt, T, seed=0, precision="fp32", burnin=burn)
+        torch.cuda.synchronize()
+        t_fwd.append(time.time() - t0)
+        vals.append(r.obs["SpSm"] / N)
+        p.close()
+    vals = np.array(vals)
+    cross = [i for i in range(len(grid) - 1) if (vals[i] - 1.0) * (vals[i + 1] - 1.0) < 0]
+    if cross:
+        i, target = cross[0], 1.0
+    else:
+        i = int(np.argmax(np.abs(np.diff(vals))))
+        target = 0.5 * (vals[i] + vals[i + 1])
+    lo, hi = float(grid[i]), float(grid[i + 1])
+    tol = 1e-6 * hi
+    torch.cuda.synchronize()
+    t0 = time.time()
+    w_root, f_root, it = twa.find_threshold(N, alpha, B, dt, T, 0, objective="spsm_n", target=target, w_lo=lo,
+                                            w_hi=hi, tol_w=tol, precision="fp32", burnin=burn)
+    torch.cuda.synchronize()
+    newton_s = time.time() - t0
+    fwd = float(np.median(t_fwd))
+    n_bisect = int(math.ceil(math.log2((hi - lo) / tol)))
+    return {"config": {"N": N, "alpha": alpha, "n_traj": B, "dt": dt, "n_steps": T, "precision": "fp32"},
+            "objective": "spsm_n", "target": target, "bracket": [lo, hi], "w_root": w_root, "residual": f_root,
+            "gradient_evaluations": it, "newton_s": newton_s, "forward_run_s": fwd,
+            "bisection_forward_runs_same_tol": n_bisect,
+            "speedup_vs_bisection": n_bisect * fwd / newton_s,
+            "uniform_scan_points_same_time": int(newton_s / fwd),
+            "uniform_scan_resolution_same_time": (hi - lo) / max(1, int(newton_s / fwd))}
+
+
 def toeplitz_rate(twa, N, w, alpha, B, dt, T, dense_value):
     """The same workload through the circulant embedding of Eq. (2) (FFT
     drift and circulant pump noise, equal in law to the dense path), FP32,
@@ -225,6 +284,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-toeplitz", action="store_true")
+    ap.add_argument("--sib", action="store_true", help="also time the semi-implicit scheme against Heun")
+    ap.add_argument("--threshold", action="store_true",
+                    help="also time a Newton threshold search against forward-only searches")
     ap.add_argument("--batch-scan", type=int, default=0,
                     help="also time the 96-point scan for this many steps (batched vs single runs)")
     args = ap.parse_args()
@@ -305,6 +367,12 @@ def main():
     if not args.no_toeplitz:
         print("[bench] Toeplitz fast path on the same workload (FP32)", file=sys.stderr, flush=True)
         line["toeplitz_path"] = toeplitz_rate(twa, N, w, alpha, B, dt, T, value)
+    if args.sib:
+        print("[bench] semi-implicit scheme vs Heun", file=sys.stderr, flush=True)
+        line["sib_vs_heun"] = sib_rate(twa, pump, B, dt, prec)
+    if args.threshold:
+        print("[bench] threshold search (N=2000, FP32)", file=sys.stderr, flush=True)
+        line["threshold"] = threshold_vs_scan(twa)
     if args.batch_scan > 0:
         print("[bench] batched scan, 96 points, %d steps" % args.batch_scan, file=sys.stderr, flush=True)
         line["batch_scan"] = batch_scan(twa, args.batch_scan)

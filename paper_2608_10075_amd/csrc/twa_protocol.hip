@@ -129,6 +129,8 @@ TWA_API int twa_find_threshold(int64_t N, double alpha, const twa_params* p, int
         if (e) return e;
         twa_params q = *p;
         q.pump = pw;
+        // the reverse sweep carries only the objective searched for
+        q.adjoint_objectives = o->objective == TWA_OBJ_G2 ? 2 : 1;
         twa_observables ob;
         std::memset(&ob, 0, sizeof(ob));
         if (grad) {
