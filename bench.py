@@ -291,7 +291,7 @@ def main():
                     help="also time the 96-point scan for this many steps (batched vs single runs)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (trajectories would shard "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (trajectories would shard "
               "across GPUs with one all-reduce of the accumulators at the end)", file=sys.stderr)
         sys.exit(2)
 
