@@ -91,3 +91,60 @@ def test_initial_signs_balanced_and_bit_layout():
     bit_x, bit_y = 2 * j, 2 * j + 1
     assert sx[7, 64 + j] == (1.0 if (int(w[bit_x // 32]) >> (bit_x % 32)) & 1 else -1.0)
     assert sy[7, 64 + j] == (1.0 if (int(w[bit_y // 32]) >> (bit_y % 32)) & 1 else -1.0)
+
+
+_ROCRAND_PROBE = r"""
+#include <rocrand/rocrand_philox4x32_10.h>
+#include <cstdint>
+#include <cstdio>
+// stdin: records of six uint32 (c0, c1, c2, c3, k0, k1); stdout: the four
+// output words of each.  rocRAND's engine keys on the 64-bit seed, puts the
+// subsequence in counter words 2..3 and offset / 4 in words 0..1.
+int main() {
+    uint32_t in[6];
+    while (std::fread(in, 4, 6, stdin) == 6) {
+        const unsigned long long seed = in[4] | ((unsigned long long)in[5] << 32);
+        const unsigned long long sub = in[2] | ((unsigned long long)in[3] << 32);
+        const unsigned long long off = 4ull * (in[0] | ((unsigned long long)in[1] << 32));
+        rocrand_device::philox4x32_10_engine e(seed, sub, off);
+        const uint4 r = e.next4();
+        const uint32_t out[4] = {r.x, r.y, r.z, r.w};
+        std::fwrite(out, 4, 4, stdout);
+    }
+    return 0;
+}
+"""
+
+
+def test_philox_matches_rocrand_engine(tmp_path):
+    """Cross-implementation check: rocRAND's Philox4x32-10 engine (its
+    header, built here for the host and run) gives the oracle's output words
+    on random counters and keys and on the carry edges of every word.  Word 1
+    stays below 2^30 so that rocRAND's 64-bit number offset (4 per counter)
+    does not wrap."""
+    import shutil
+    import subprocess
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc) or not os.path.exists("/opt/rocm/include/rocrand/rocrand_philox4x32_10.h"):
+        pytest.skip("hipcc or the rocRAND headers are not installed")
+    src = tmp_path / "philox_rocrand.cpp"
+    src.write_text(_ROCRAND_PROBE)
+    exe = tmp_path / "philox_rocrand"
+    subprocess.run([hipcc, "-O2", "-x", "hip", "--offload-host-only", str(src), "-o", str(exe)], check=True,
+                   capture_output=True)
+    rng = np.random.default_rng(11)
+    n = 1 << 16
+    m32 = 0xFFFFFFFF
+    edge = np.array([[0, 0, 0, 0], [m32, 0, 0, 0], [m32, 5, m32, m32], [1, 2, 3, 4], [m32, (1 << 30) - 1, m32, m32]],
+                    dtype=np.uint64)
+    for k0, k1 in [(0, 0), (0xDEADBEEF, 0x12345678), (m32, m32), (7, 0)]:
+        c = rng.integers(0, 1 << 32, size=(n, 4), dtype=np.uint64)
+        c[:, 1] >>= np.uint64(2)
+        c = np.concatenate([edge, c])
+        rec = np.empty((c.shape[0], 6), dtype=np.uint32)
+        rec[:, :4] = c
+        rec[:, 4], rec[:, 5] = k0, k1
+        out = subprocess.run([str(exe)], input=rec.tobytes(), check=True, capture_output=True).stdout
+        got = np.frombuffer(out, dtype=np.uint32).reshape(-1, 4)
+        want = np.stack(philox.philox4x32_10(c[:, 0], c[:, 1], c[:, 2], c[:, 3], k0, k1), axis=1)
+        assert np.array_equal(got.astype(np.uint64), want)
