@@ -148,6 +148,90 @@ __device__ __forceinline__ void stg4perp(typename Prec<PREC>::G* cx, typename Pr
     stg4<PREC>(cy, m);
 }
 
+// Epilogue streams as raw buffers: the descriptor's base is the wave's first
+// element of an array (wave-uniform, scalar registers), the lane adds one
+// 32-bit byte offset (voff) and the block one uniform byte offset, so every
+// stream costs one offset VGPR in total instead of a 64-bit address.  Loads
+// take the block offset in the scalar offset field; stores take it in voff
+// with a zero scalar offset: with a register scalar offset the compiler puts
+// no wait state between a 128-bit store and a VALU write of its data
+// registers, and the store then wrote the overwritten value (observed on
+// gfx950 in the first dword of a store's data).
+typedef __amdgpu_buffer_rsrc_t Rsrc;
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ Rsrc wave_rsrc(const void* base, int64_t bytes) {
+    const uint32_t n = bytes >= (int64_t)0xFFFFFFFF ? 0xFFFFFFFFu : (uint32_t)bytes;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)n, 0x00020000);
+}
+template <typename S>
+__device__ __forceinline__ void bld4(Rsrc r, uint32_t voff, uint32_t soff, S (&v)[4]) {
+    if constexpr (sizeof(S) == 4) {
+        const f32x4 t = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+        v[0] = t[0]; v[1] = t[1]; v[2] = t[2]; v[3] = t[3];
+    } else {
+        const f64x2 t0 = __builtin_bit_cast(f64x2, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+        const f64x2 t1 = __builtin_bit_cast(f64x2, __builtin_amdgcn_raw_buffer_load_b128(r, voff + 16, soff, 0));
+        v[0] = t0[0]; v[1] = t0[1]; v[2] = t1[0]; v[3] = t1[1];
+    }
+}
+template <typename S>
+__device__ __forceinline__ void bst4(Rsrc r, uint32_t voff, const S (&v)[4]) {
+    if constexpr (sizeof(S) == 4) {
+        const f32x4 t = {v[0], v[1], v[2], v[3]};
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, t), r, voff, 0, 0);
+    } else {
+        const f64x2 t0 = {v[0], v[1]}, t1 = {v[2], v[3]};
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, t0), r, voff, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, t1), r, voff + 16, 0, 0);
+    }
+}
+// four operand values (contraction type) from state values
+template <int PREC>
+__device__ __forceinline__ void bstg4(Rsrc r, uint32_t voff, const typename Prec<PREC>::S (&v)[4]) {
+    typedef typename Prec<PREC>::G G;
+    if constexpr (sizeof(G) == 2) {
+        uint16_t h[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) h[q] = __builtin_bit_cast(uint16_t, Prec<PREC>::to_g(v[q]));
+        const u32x2 t = {(uint32_t)h[0] | ((uint32_t)h[1] << 16), (uint32_t)h[2] | ((uint32_t)h[3] << 16)};
+        __builtin_amdgcn_raw_buffer_store_b64(t, r, voff, 0, 0);
+    } else {
+        typename Prec<PREC>::S g[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) g[q] = Prec<PREC>::to_g(v[q]);
+        bst4(r, voff, g);
+    }
+}
+// operand store of a state-like value: one block, or for the split form the
+// (hi, lo, hi) blocks blk bytes apart
+template <int PREC>
+__device__ __forceinline__ void bstg4s(Rsrc r, uint32_t voff, uint32_t blk, const typename Prec<PREC>::S (&v)[4]) {
+    if constexpr (Prec<PREC>::SPLIT == 3) {
+        uint16_t hi[4], lo[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) bf16_split(v[q], hi[q], lo[q]);
+        const u32x2 th = {(uint32_t)hi[0] | ((uint32_t)hi[1] << 16), (uint32_t)hi[2] | ((uint32_t)hi[3] << 16)};
+        const u32x2 tl = {(uint32_t)lo[0] | ((uint32_t)lo[1] << 16), (uint32_t)lo[2] | ((uint32_t)lo[3] << 16)};
+        __builtin_amdgcn_raw_buffer_store_b64(th, r, voff, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b64(tl, r, voff + blk, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b64(th, r, voff + 2 * blk, 0, 0);
+    } else {
+        bstg4<PREC>(r, voff, v);
+    }
+}
+// coherent exchange: (v^y, -v^x) into the perpendicular blocks of the x and y
+// columns (byte offsets vx_off, vy_off)
+template <int PREC>
+__device__ __forceinline__ void bstg4perp(Rsrc r, uint32_t vx_off, uint32_t vy_off,
+                                          const typename Prec<PREC>::S (&vx)[4],
+                                          const typename Prec<PREC>::S (&vy)[4]) {
+    typename Prec<PREC>::S m[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) m[q] = -vx[q];
+    bstg4<PREC>(r, vx_off, vy);
+    bstg4<PREC>(r, vy_off, m);
+}
+
 // operand store of a state-like value: one block, or for the split form the
 // (hi, lo, hi) blocks blk elements apart
 template <int PREC>
@@ -422,6 +506,64 @@ __device__ __forceinline__ void stage_tile(const GemmArgs<PREC>& a, const int mt
     // ---- epilogue: fused Heun stage on (spin i, trajectory k)
     const S c1 = a.c1, c2 = a.c2;
     const int64_t SP = Bp * P;   // plane size
+    // The primal kinds load the state (and, in the corrector, the predictor
+    // field) of the next (p, bi) block before the current block is computed
+    // and stored, so one block of loads is always in flight behind the stores
+    // instead of every block waiting out a full memory round trip.
+    // Their addresses: a buffer descriptor per array plane based at the wave's
+    // first element, one lane byte offset per layout (state planes [k][P],
+    // operand columns of the next contraction) and a uniform byte offset per
+    // block (p, bi).
+    constexpr bool PF = KD == KIND_PRIMAL || KD == KIND_SIB;
+    constexpr int NPF = STAGE == 2 ? 5 : 3;
+    constexpr int NBLK = (BJ / 2) * BI;
+    const int wvu = __builtin_amdgcn_readfirstlane(wave);
+    const int64_t wm0u = (int64_t)(wvu % WMW) * WM, kw0 = k0t + (int64_t)(wvu / WMW) * (WN / 2);
+    const int64_t eb_s = kw0 * P + m0 + wm0u;                 // wave base in a state plane
+    const int64_t rem_s = (SP - eb_s) * (int64_t)sizeof(S);
+    const uint32_t lane_s = (uint32_t)(((lane & 15) * P + 4 * (lane >> 4)) * (int64_t)sizeof(S));
+    auto so_s = [&](const int p, const int bi) { return (uint32_t)((16 * p * P + 16 * bi) * (int64_t)sizeof(S)); };
+    auto plane = [&](const S* arr, const int c) { return wave_rsrc(arr + c * SP + eb_s, rem_s); };
+    // operand columns: trajectory kw0 + 16 p + (lane & 15) has columns
+    // opcol(k, c) = 32 (kw0 / 16 + p) + 16 c + (lane & 15), rows m0 + wm0u + ...
+    auto op_rsrc = [&](const G* arr, const int64_t ld) {
+        const int64_t eb = 32 * (kw0 >> 4) * ld + m0 + wm0u;
+        return wave_rsrc(arr + eb, (2 * Bp * ld - eb) * (int64_t)sizeof(G));
+    };
+    auto op_lane = [&](const int64_t ld) {
+        return (uint32_t)(((lane & 15) * ld + 4 * (lane >> 4)) * (int64_t)sizeof(G));
+    };
+    auto so_op = [&](const int64_t ld, const int p, const int c, const int bi, const int64_t row) {
+        return (uint32_t)(((32 * p + 16 * c) * ld + row + 16 * bi) * (int64_t)sizeof(G));
+    };
+    const uint32_t blk_b = (uint32_t)(P * (int64_t)sizeof(G));   // split (hi, lo, hi) block stride
+    Rsrc rs[3], ry[2], rop;
+    uint32_t ld_d = 0, ld_x = 0;
+    if constexpr (PF) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) rs[c] = plane(a.s_cur, c);
+#pragma unroll
+        for (int c = 0; c < 2; ++c) ry[c] = plane(a.Y, c);
+        if constexpr (STAGE == 1) {
+            rop = op_rsrc(a.Dop, a.ldd);
+            ld_d = op_lane(a.ldd);
+        } else {
+            rop = op_rsrc(a.Xnext, a.ldxn);
+            ld_x = op_lane(a.ldxn);
+        }
+    }
+    S pfn[NPF][4];
+    auto pf_load = [&](const int p, const int bi) {
+        const uint32_t so = so_s(p, bi);
+        bld4(rs[0], lane_s, so, pfn[0]);
+        bld4(rs[1], lane_s, so, pfn[1]);
+        bld4(rs[2], lane_s, so, pfn[2]);
+        if constexpr (NPF == 5) {
+            bld4(ry[0], lane_s, so, pfn[3]);
+            bld4(ry[1], lane_s, so, pfn[4]);
+        }
+    };
+    if constexpr (PF) pf_load(0, 0);
 #pragma unroll
     for (int p = 0; p < BJ / 2; ++p) {
         const int kl = wn0 / 2 + 16 * p + (lane & 15);
@@ -434,8 +576,30 @@ __device__ __forceinline__ void stage_tile(const GemmArgs<PREC>& a, const int mt
         for (int bi = 0; bi < BI; ++bi) {
             const int64_t i0 = m0 + wm0 + 16 * bi + 4 * (lane >> 4);
             const int64_t off = k * P + i0;
-            S x[4], y[4], z[4];
-            if constexpr (KD != KIND_STORE) {
+            S x[4], y[4], z[4], fyx[4], fyy[4], fdx[4], fdy[4], fdz[4];
+            if constexpr (PF) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    x[r] = pfn[0][r];
+                    y[r] = pfn[1][r];
+                    z[r] = pfn[2][r];
+                    if constexpr (NPF == 5) {
+                        fyx[r] = pfn[3][r];
+                        fyy[r] = pfn[4][r];
+                    }
+                }
+                // the stored predictor increment (when kept) is read before the
+                // next block's loads are issued, so that its wait does not
+                // include them
+                if constexpr (KD == KIND_PRIMAL && STAGE == 2) {
+                    if (a.dlt) {
+                        bld4(plane(a.dlt, 0), lane_s, so_s(p, bi), fdx);
+                        bld4(plane(a.dlt, 1), lane_s, so_s(p, bi), fdy);
+                        bld4(plane(a.dlt, 2), lane_s, so_s(p, bi), fdz);
+                    }
+                }
+                if (p * BI + bi + 1 < NBLK) pf_load((p * BI + bi + 1) / BI, (p * BI + bi + 1) % BI);
+            } else if constexpr (KD != KIND_STORE) {
                 ld4(a.s_cur + off, x);
                 ld4(a.s_cur + SP + off, y);
                 ld4(a.s_cur + 2 * SP + off, z);
@@ -456,15 +620,16 @@ __device__ __forceinline__ void stage_tile(const GemmArgs<PREC>& a, const int mt
                     ps2 += z[r] + dz[r];
                 }
                 if (a.dlt) {
-                    st4(a.dlt + off, dx);
-                    st4(a.dlt + SP + off, dy);
-                    st4(a.dlt + 2 * SP + off, dz);
+                    bst4(plane(a.dlt, 0), lane_s + so_s(p, bi), dx);
+                    bst4(plane(a.dlt, 1), lane_s + so_s(p, bi), dy);
+                    bst4(plane(a.dlt, 2), lane_s + so_s(p, bi), dz);
                 }
-                st4(a.Y + off, yx);
-                st4(a.Y + SP + off, yy);
-                stg4s<PREC>(a.Dop + opcol(k, 0) * a.ldd + i0, P, dx);
-                stg4s<PREC>(a.Dop + opcol(k, 1) * a.ldd + i0, P, dy);
-                if (a.coh) stg4perp<PREC>(a.Dop + opcol(k, 0) * a.ldd + P + i0, a.Dop + opcol(k, 1) * a.ldd + P + i0, dx, dy);
+                bst4(ry[0], lane_s + so_s(p, bi), yx);
+                bst4(ry[1], lane_s + so_s(p, bi), yy);
+                bstg4s<PREC>(rop, ld_d + so_op(a.ldd, p, 0, bi, 0), blk_b, dx);
+                bstg4s<PREC>(rop, ld_d + so_op(a.ldd, p, 1, bi, 0), blk_b, dy);
+                if (a.coh)
+                    bstg4perp<PREC>(rop, ld_d + so_op(a.ldd, p, 0, bi, P), ld_d + so_op(a.ldd, p, 1, bi, P), dx, dy);
                 if constexpr (QSNAP) {
                     S qx[4], qy[4];
 #pragma unroll
@@ -472,8 +637,8 @@ __device__ __forceinline__ void stage_tile(const GemmArgs<PREC>& a, const int mt
                         qx[r] = acc[bi][2 * p][r] - accW[bi][2 * p][r];
                         qy[r] = acc[bi][2 * p + 1][r] - accW[bi][2 * p + 1][r];
                     }
-                    st4(a.Sout + off, qx);
-                    st4(a.Sout + SP + off, qy);
+                    bst4(plane(a.Sout, 0), lane_s + so_s(p, bi), qx);
+                    bst4(plane(a.Sout, 1), lane_s + so_s(p, bi), qy);
                 }
             } else if constexpr (KD == KIND_SIB && STAGE == 1) {
                 // predictor: the midpoint rule with the field at s_n
@@ -491,17 +656,18 @@ __device__ __forceinline__ void stage_tile(const GemmArgs<PREC>& a, const int mt
                     ps1 += py;
                     ps2 += pz;
                 }
-                st4(a.Y + off, yx);
-                st4(a.Y + SP + off, yy);
-                stg4s<PREC>(a.Dop + opcol(k, 0) * a.ldd + i0, P, dx);
-                stg4s<PREC>(a.Dop + opcol(k, 1) * a.ldd + i0, P, dy);
-                if (a.coh) stg4perp<PREC>(a.Dop + opcol(k, 0) * a.ldd + P + i0, a.Dop + opcol(k, 1) * a.ldd + P + i0, dx, dy);
+                bst4(ry[0], lane_s + so_s(p, bi), yx);
+                bst4(ry[1], lane_s + so_s(p, bi), yy);
+                bstg4s<PREC>(rop, ld_d + so_op(a.ldd, p, 0, bi, 0), blk_b, dx);
+                bstg4s<PREC>(rop, ld_d + so_op(a.ldd, p, 1, bi, 0), blk_b, dy);
+                if (a.coh)
+                    bstg4perp<PREC>(rop, ld_d + so_op(a.ldd, p, 0, bi, P), ld_d + so_op(a.ldd, p, 1, bi, P), dx, dy);
             } else if constexpr (KD == KIND_SIB && STAGE == 2) {
                 // corrector: the midpoint rule from s_n with the field at the
                 // midpoint m = s_n + D/2: contraction Y1 + A_left D / 2, sums (S_n + S~)/2
-                S yx[4], yy[4], nx[4], ny[4], nz[4];
-                ld4(a.Y + off, yx);
-                ld4(a.Y + SP + off, yy);
+                S nx[4], ny[4], nz[4];
+                const S (&yx)[4] = fyx;
+                const S (&yy)[4] = fyy;
                 const S hxm = c1 * (S(0.5) * (sT[kl][0] + Sx)) + c2 * sG[kl][0];
                 const S hym = c1 * (S(0.5) * (sT[kl][1] + Sy)) + c2 * sG[kl][1];
 #pragma unroll
@@ -513,22 +679,28 @@ __device__ __forceinline__ void stage_tile(const GemmArgs<PREC>& a, const int mt
                     ps1 += ny[r];
                     ps2 += nz[r];
                 }
-                st4(a.s_next + off, nx);
-                st4(a.s_next + SP + off, ny);
-                st4(a.s_next + 2 * SP + off, nz);
-                stg4s<PREC>(a.Xnext + opcol(k, 0) * a.ldxn + i0, P, nx);
-                stg4s<PREC>(a.Xnext + opcol(k, 1) * a.ldxn + i0, P, ny);
+                bst4(plane(a.s_next, 0), lane_s + so_s(p, bi), nx);
+                bst4(plane(a.s_next, 1), lane_s + so_s(p, bi), ny);
+                bst4(plane(a.s_next, 2), lane_s + so_s(p, bi), nz);
+                bstg4s<PREC>(rop, ld_x + so_op(a.ldxn, p, 0, bi, 0), blk_b, nx);
+                bstg4s<PREC>(rop, ld_x + so_op(a.ldxn, p, 1, bi, 0), blk_b, ny);
                 if (a.coh)
-                    stg4perp<PREC>(a.Xnext + opcol(k, 0) * a.ldxn + 2 * P + i0,
-                                   a.Xnext + opcol(k, 1) * a.ldxn + 2 * P + i0, nx, ny);
+                    bstg4perp<PREC>(rop, ld_x + so_op(a.ldxn, p, 0, bi, 2 * P), ld_x + so_op(a.ldxn, p, 1, bi, 2 * P),
+                                    nx, ny);
             } else if constexpr (KD == KIND_PRIMAL && STAGE == 2) {
                 S dx[4], dy[4], dz[4], yx[4], yy[4], nx[4], ny[4], nz[4];
-                ld4(a.Y + off, yx);
-                ld4(a.Y + SP + off, yy);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    yx[r] = fyx[r];
+                    yy[r] = fyy[r];
+                }
                 if (a.dlt) {
-                    ld4(a.dlt + off, dx);
-                    ld4(a.dlt + SP + off, dy);
-                    ld4(a.dlt + 2 * SP + off, dz);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        dx[r] = fdx[r];
+                        dy[r] = fdy[r];
+                        dz[r] = fdz[r];
+                    }
                 } else {
                     // the predictor increment, recomputed exactly as the predictor
                     // stage formed it (same operands, same operation order)
@@ -557,19 +729,19 @@ __device__ __forceinline__ void stage_tile(const GemmArgs<PREC>& a, const int mt
                     ps1 += ny[r];
                     ps2 += nz[r];
                 }
-                st4(a.s_next + off, nx);
-                st4(a.s_next + SP + off, ny);
-                st4(a.s_next + 2 * SP + off, nz);
+                bst4(plane(a.s_next, 0), lane_s + so_s(p, bi), nx);
+                bst4(plane(a.s_next, 1), lane_s + so_s(p, bi), ny);
+                bst4(plane(a.s_next, 2), lane_s + so_s(p, bi), nz);
                 if (a.store_y2) {
-                    S* yo = a.Y2out ? a.Y2out : a.Y;
-                    st4(yo + off, yx);
-                    st4(yo + SP + off, yy);
+                    const S* yo = a.Y2out ? a.Y2out : a.Y;
+                    bst4(plane(yo, 0), lane_s + so_s(p, bi), yx);
+                    bst4(plane(yo, 1), lane_s + so_s(p, bi), yy);
                 }
-                stg4s<PREC>(a.Xnext + opcol(k, 0) * a.ldxn + i0, P, nx);
-                stg4s<PREC>(a.Xnext + opcol(k, 1) * a.ldxn + i0, P, ny);
+                bstg4s<PREC>(rop, ld_x + so_op(a.ldxn, p, 0, bi, 0), blk_b, nx);
+                bstg4s<PREC>(rop, ld_x + so_op(a.ldxn, p, 1, bi, 0), blk_b, ny);
                 if (a.coh)
-                    stg4perp<PREC>(a.Xnext + opcol(k, 0) * a.ldxn + 2 * P + i0,
-                                   a.Xnext + opcol(k, 1) * a.ldxn + 2 * P + i0, nx, ny);
+                    bstg4perp<PREC>(rop, ld_x + so_op(a.ldxn, p, 0, bi, 2 * P), ld_x + so_op(a.ldxn, p, 1, bi, 2 * P),
+                                    nx, ny);
             } else if constexpr (KD == KIND_TANGENT && STAGE == 1) {
                 const S tSx = sT[kl][0], tSy = sT[kl][1];
                 const S* tc = a.t_cur + cp * a.t_state_copy;
