@@ -920,6 +920,13 @@ __device__ __forceinline__ void stage_tile(const GemmArgs<PREC>& a, const int mt
                 stg4<PREC>(txo + opcol(k, 0) * a.ldxn + i0, nu);
                 stg4<PREC>(txo + opcol(k, 1) * a.ldxn + i0, nv);
             }
+            // the partial sums are formed inside their block (an empty asm pins
+            // each sum in a register here): sunk to the end of the group, they
+            // kept every block's state live and spilled it
+            if constexpr (PF) {
+                asm volatile("" : "+v"(ps0), "+v"(ps1), "+v"(ps2));
+                __builtin_amdgcn_sched_barrier(0);
+            }
         }
         // partial spin sums of the new values: lanes sharing a trajectory,
         // then waves along M, in a fixed order
