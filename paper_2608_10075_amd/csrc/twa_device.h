@@ -35,15 +35,16 @@ __device__ __forceinline__ U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1) {
 enum : uint32_t { TAG_PUMP = 0u, TAG_COLLECTIVE = 1u, TAG_INIT = 2u };
 
 // Box-Muller (Box & Muller 1958) on two words.  u1 = ((a >> 8) + 1) 2^-24 in
-// (0, 1] and u2 = (b >> 8) 2^-24 are exact in binary32.
+// (0, 1] and u2 = (b >> 8) 2^-24 are exact in binary32.  Binary32 uses the
+// hardware transcendentals: v_log_f32 (log2; ln u1 = ln 2 log2 u1),
+// v_sqrt_f32, and v_sin_f32 / v_cos_f32, which take their argument in
+// revolutions (sin 2 pi u2 directly, u2 in [0, 1)).
 __device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, float& z0, float& z1) {
     const float u1 = (float)((a >> 8) + 1u) * 5.9604644775390625e-08f;
     const float u2 = (float)(b >> 8) * 5.9604644775390625e-08f;
-    const float r = sqrtf(-2.0f * logf(u1));
-    float s, c;
-    sincospif(2.0f * u2, &s, &c);
-    z0 = r * c;
-    z1 = r * s;
+    const float r = __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u1));
+    z0 = r * __builtin_amdgcn_cosf(u2);
+    z1 = r * __builtin_amdgcn_sinf(u2);
 }
 __device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, double& z0, double& z1) {
     const double u1 = (double)((a >> 8) + 1u) * 5.9604644775390625e-08;
