@@ -30,6 +30,12 @@
 #include "twa_internal.h"
 #include "twa_run.h"
 
+// Multiply-adds in this file are fused (the library is otherwise built with
+// -ffp-contract=off, so that the stage kernels round alike in every variant
+// they are inlined into): the transforms are bound by VALU issue and no other
+// kernel has to reproduce their rounding.
+#pragma clang fp contract(fast)
+
 namespace twa {
 namespace {
 
