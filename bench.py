@@ -208,6 +208,29 @@ def sib_rate(twa, pump, B, dt, prec, steps=400):
     return out
 
 
+def two_time_cost(twa, N=1000, w=1.0, alpha=1.0, B=4096, dt=1e-4, T=4000, lags=500, prec="fp32"):
+    """Cost of the two-time correlation (two tangent-linear response copies
+    propagated from the window start, and the lag sums) on the N = 1000,
+    4096-trajectory workload: device time of a run with the lag window over
+    the last half against the same run without it, and the cost per step
+    inside the window relative to a plain step."""
+    pump = twa.build_pump(N, w, alpha)
+    burn = T // 2
+    stride = max(1, (T - burn) // lags)
+    twa.run(pump, B, dt, 64, seed=0, precision=prec)
+    plain = twa.run(pump, B, dt, T, seed=0, precision=prec, burnin=burn).obs["kernel_ms"]
+    twa.run(pump, B, dt, 64, seed=0, precision=prec, burnin=32, n_lags=16, lag_stride=2)
+    r = twa.run(pump, B, dt, T, seed=0, precision=prec, burnin=burn, n_lags=lags, lag_stride=stride)
+    lagged = r.obs["kernel_ms"]
+    per_step = plain / T
+    window = (lagged - plain) / (T - burn) + per_step
+    return {"config": {"N": N, "w": w, "alpha": alpha, "n_traj": B, "dt": dt, "n_steps": T, "burnin": burn,
+                       "n_lags": lags, "lag_stride": stride, "precision": prec},
+            "plain_ms": plain, "with_lags_ms": lagged, "plain_ms_per_step": per_step,
+            "window_ms_per_step": window, "window_cost_ratio": window / per_step,
+            "linewidth": r.obs.get("linewidth")}
+
+
 def threshold_vs_scan(twa, N=2000, alpha=1.0, B=2048, dt=1e-4, T=2048):
     """Locating a threshold by Newton steps with adjoint gradients against
     forward-only searches, at fixed noise: <S+S->/N = target on a bracket
@@ -287,6 +310,8 @@ def main():
     ap.add_argument("--sib", action="store_true", help="also time the semi-implicit scheme against Heun")
     ap.add_argument("--threshold", action="store_true",
                     help="also time a Newton threshold search against forward-only searches")
+    ap.add_argument("--two-time", action="store_true",
+                    help="also time the two-time correlation window (N = 1000, 4096 trajectories, FP32)")
     ap.add_argument("--batch-scan", type=int, default=0,
                     help="also time the 96-point scan for this many steps (batched vs single runs)")
     args = ap.parse_args()
@@ -373,6 +398,9 @@ def main():
     if args.threshold:
         print("[bench] threshold search (N=2000, FP32)", file=sys.stderr, flush=True)
         line["threshold"] = threshold_vs_scan(twa)
+    if args.two_time:
+        print("[bench] two-time correlation window (N=1000, FP32)", file=sys.stderr, flush=True)
+        line["two_time"] = two_time_cost(twa)
     if args.batch_scan > 0:
         print("[bench] batched scan, 96 points, %d steps" % args.batch_scan, file=sys.stderr, flush=True)
         line["batch_scan"] = batch_scan(twa, args.batch_scan)
