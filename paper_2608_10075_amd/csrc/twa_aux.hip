@@ -318,12 +318,9 @@ __global__ __launch_bounds__(256) void observe_kernel(int64_t B, int64_t Bp, int
         l = (kst - burnin) / stride;
     double acc6[6] = {0, 0, 0, 0, 0, 0};
     for (int64_t k = klo + threadIdx.x; k < khi; k += blockDim.x) {
-        S Sx = 0, Sy = 0, Sz = 0;
-        for (int64_t q = 0; q < nmt; ++q) {
-            Sx += part[(0 * nmt + q) * Bp + k];
-            Sy += part[(1 * nmt + q) * Bp + k];
-            Sz += part[(2 * nmt + q) * Bp + k];
-        }
+        S sxyz[3];
+        tile_sums<S, 3>(part, nmt, Bp, k, 0, sxyz);
+        const S Sx = sxyz[0], Sy = sxyz[1], Sz = sxyz[2];
         if (in_window) {
             const S T2 = S(0.25) * (Sx * Sx + Sy * Sy);
             const S v[5] = {T2, T2 * Sz, T2 * T2, Sz, Sz * Sz};
@@ -340,14 +337,10 @@ __global__ __launch_bounds__(256) void observe_kernel(int64_t B, int64_t Bp, int
             acc6[1] += 0.25 * ((double)Sy * x0 - (double)Sx * y0);
             if (tangents) {
                 for (int cp = 0; cp < 2; ++cp) {
-                    const S* tp = tpart + cp * tpart_copy;
-                    S tx = 0, ty = 0;
-                    for (int64_t q = 0; q < nmt; ++q) {
-                        tx += tp[(0 * nmt + q) * Bp + k];
-                        ty += tp[(1 * nmt + q) * Bp + k];
-                    }
-                    acc6[2 + 2 * cp] += (double)tx;
-                    acc6[3 + 2 * cp] += (double)ty;
+                    S txy[2];
+                    tile_sums<S, 2>(tpart + cp * tpart_copy, nmt, Bp, k, 0, txy);
+                    acc6[2 + 2 * cp] += (double)txy[0];
+                    acc6[3 + 2 * cp] += (double)txy[1];
                 }
             }
         }

@@ -96,12 +96,9 @@ __global__ __launch_bounds__(256) void observe_grouped_kernel(const PointDesc* _
     const S* part = static_cast<const S*>(d.part0);
     S* mom = static_cast<S*>(d.mom);
     for (int64_t k = threadIdx.x; k < d.B; k += blockDim.x) {
-        S Sx = 0, Sy = 0, Sz = 0;
-        for (int64_t q = 0; q < d.nmt; ++q) {
-            Sx += part[(0 * d.nmt + q) * d.Bp + k];
-            Sy += part[(1 * d.nmt + q) * d.Bp + k];
-            Sz += part[(2 * d.nmt + q) * d.Bp + k];
-        }
+        S sxyz[3];
+        tile_sums<S, 3>(part, d.nmt, d.Bp, k, 0, sxyz);
+        const S Sx = sxyz[0], Sy = sxyz[1], Sz = sxyz[2];
         const S T2 = S(0.25) * (Sx * Sx + Sy * Sy);
         const S v[5] = {T2, T2 * Sz, T2 * T2, Sz, Sz * Sz};
 #pragma unroll

@@ -199,6 +199,30 @@ int launch_toeplitz_run(const Geometry& g, const EnsembleBuffers& b, const StepC
 
 // pump (twa_pump.hip): the Eq. (2) pump of a handle rescaled to amplitude w
 int pump_scaled(const twa_pump* base, double w, twa_pump** out);
+// sum over the nmt M-tile partials of trajectory k in tile order, for the
+// channels c0 .. c0 + NC - 1; the loads of eight tiles are issued before
+// their additions (the order of the additions is unchanged)
+template <typename S, int NC>
+__device__ __forceinline__ void tile_sums(const S* part, int64_t nmt, int64_t Bp, int64_t k, int c0, S (&out)[NC]) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) out[c] = 0;
+    int64_t q = 0;
+    for (; q + 8 <= nmt; q += 8) {
+        S v[NC][8];
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[c][u] = part[((c0 + c) * nmt + q + u) * Bp + k];
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+            for (int u = 0; u < 8; ++u) out[c] += v[c][u];
+    }
+    for (; q < nmt; ++q)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) out[c] += part[((c0 + c) * nmt + q) * Bp + k];
+}
+
 }  // namespace twa
 
 struct twa_pump {
