@@ -182,6 +182,23 @@ def test_determinism():
     assert np.array_equal(a.corr_blocks, b.corr_blocks)
 
 
+def test_blas_thread_count_changes_only_rounding():
+    """At a fixed BLAS thread count the oracle is bitwise reproducible; the
+    matrix products are BLAS calls whose summation split depends on the
+    thread count, so 1 and 4 threads agree to rounding (measured 2e-15 on
+    unit spins), not bit for bit."""
+    from threadpoolctl import threadpool_limits
+    cfg = twa.RunConfig(n_spin=300, w=2.0, alpha=1.0, n_traj=64, dt=1e-4, n_steps=30, seed=2)
+    with threadpool_limits(limits=1):
+        a, a2 = twa.run(cfg), twa.run(cfg)
+    with threadpool_limits(limits=4):
+        b = twa.run(cfg)
+    for u, u2, v in zip(a.final_state, a2.final_state, b.final_state):
+        assert np.array_equal(u, u2)
+        assert np.max(np.abs(u - v)) < 1e-12
+    assert np.max(np.abs(a.traj_moments - b.traj_moments) / (np.abs(a.traj_moments) + 1e-300)) < 1e-12
+
+
 def test_trajectory_subset_equals_rows_of_full_ensemble():
     """Trajectories are independent (their noise counters carry the trajectory
     index), so integrating a subset reproduces those rows of the full run."""
