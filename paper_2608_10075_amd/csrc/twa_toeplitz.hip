@@ -542,7 +542,9 @@ int launch_s(int logm, const Geometry& g, const EnsembleBuffers& b, const StepCo
             case 11: return launch_t<S, 11, 4>(g, b, c, tw, spec, step0, n, cur, st);
             case 12: return launch_t<S, 12, 4>(g, b, c, tw, spec, step0, n, cur, st);
             case 13: return launch_t<S, 13, 4>(g, b, c, tw, spec, step0, n, cur, st);
-            case 14: return launch_t<S, 14, 4>(g, b, c, tw, spec, step0, n, cur, st);
+            // 512 threads of 32 values: at 1024 threads of 16 each the kernel
+            // spilled 87 registers (128 per thread at that size)
+            case 14: return launch_t<S, 14, 5>(g, b, c, tw, spec, step0, n, cur, st);
         }
     }
     set_error("Toeplitz path: embedding size out of range");
