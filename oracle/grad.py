@@ -12,7 +12,10 @@ Eq. (2) and its PSD square root F.  Derivatives are propagated forward
   ensemble-averaged moments; g2 by the quotient rule on the averages.
 
 ``fd_gradients`` gives the central finite differences at identical Philox
-streams used to cross-check.
+streams used to cross-check.  ``heun_step_vjp`` is the transpose of the
+tangent-linear Heun step (reverse mode), the operation the library's reverse
+sweep applies step by step; the dot-product identity <u, J v> = <J^T u, v>
+against ``twa.heun_step_tangent`` pins it.
 """
 from __future__ import annotations
 
@@ -114,3 +117,36 @@ def fd_gradients(cfg: RunConfig, h: float = 1e-4, params=("w", "alpha")):
         for name in ("Sz", "SpSm", "g2"):
             out["d_%s_d%s" % (name, k)] = (vals[0][name] - vals[1][name]) / (2 * h)
     return out
+
+
+def _incr_vjp(state, mu, fields_dt, W, gamma, dt):
+    """Transpose of the linearisation of one increment of Eq. (S1) at ``state``
+    with fixed noise: cotangent ``mu`` = (mu^x, mu^y, mu^z) of the increment
+    f = (s^z H^x, s^z H^y, -(s^x H^x + s^y H^y)), H^a the dt-scaled fields
+    ``fields_dt``, returns the cotangent of the state.  The fields depend on
+    the state through H^a_i = (Gamma/2 sum_j s^a_j - 1/2 sum_j w_ij s^a_j) dt + noise."""
+    x, y, z = state
+    hx, hy = fields_dt
+    ux, uy, uz = mu
+    # direct dependence of f on s at fixed H
+    cx = -uz * hx
+    cy = -uz * hy
+    cz = ux * hx + uy * hy
+    # dependence through H: nu^a = (df/dH^a)^T mu
+    nx = ux * z - uz * x
+    ny = uy * z - uz * y
+    cx = cx + (0.5 * gamma * nx.sum(axis=1)[:, None] - 0.5 * (nx @ W)) * dt
+    cy = cy + (0.5 * gamma * ny.sum(axis=1)[:, None] - 0.5 * (ny @ W)) * dt
+    return cx, cy, cz
+
+
+def heun_step_vjp(state, cot, W, gamma, dt, dxi, dchi):
+    """Reverse mode of one stochastic Heun step s' = s + (f(s) + f(s + f(s)))/2
+    at fixed noise: the cotangent of s' -> the cotangent of s."""
+    from .twa import heun_step
+    _, (d1, pred, d2) = heun_step(state, W, gamma, dt, dxi, dchi)
+    mu2 = tuple(0.5 * c for c in cot)
+    lam_pred = _incr_vjp(pred, mu2, d2[3], W, gamma, dt)
+    mu1 = tuple(0.5 * c + lp for c, lp in zip(cot, lam_pred))
+    lam_s = _incr_vjp(state, mu1, d1[3], W, gamma, dt)
+    return tuple(c + lp + ls for c, lp, ls in zip(cot, lam_pred, lam_s))

@@ -63,6 +63,24 @@ def build_pump(n_spin: int, w: float, alpha: float) -> Pump:
     return Pump(n_spin, float(w), float(alpha), W, F, lam, V, float(lam[0]), float(lam[-1]))
 
 
+def build_pump_dense(W: np.ndarray) -> Pump:
+    """Channel decomposition and PSD noise factor of an arbitrary symmetric PSD
+    pump matrix (the general pump of the Perspectives), with the same square
+    root as ``build_pump``; w and alpha are recorded as NaN."""
+    W = np.array(W, dtype=np.float64)
+    n = W.shape[0]
+    if W.shape != (n, n) or not np.all(np.isfinite(W)) or np.max(np.abs(W - W.T)) > 0:
+        raise ValueError("need a finite symmetric square matrix")
+    lam, V = np.linalg.eigh(W)
+    if lam[0] < -1e-10 * max(float(lam[-1]), 0.0):
+        raise ValueError("pump matrix is not positive semidefinite")
+    tol = 8.0 * n * np.finfo(np.float64).eps * max(float(lam[-1]), 0.0)
+    lam_c = np.where(lam > tol, lam, 0.0)
+    F = (V * np.sqrt(lam_c)) @ V.T
+    F = 0.5 * (F + F.T)
+    return Pump(n, float("nan"), float("nan"), W, F, lam, V, float(lam[0]), float(lam[-1]))
+
+
 def normalised_pump(p: Pump, gamma: float = 1.0) -> float:
     """w~ = w_max / (Gamma N) (main text, after Eq. (3))."""
     return p.lam_max / (gamma * p.n_spin)

@@ -188,11 +188,28 @@ def fields(state, W, gamma, dt, dxi, dchi):
     return increment(state, W, gamma, dt, dxi, dchi)[3]
 
 
+def _solve3(M, r):
+    """Solve the 3 x 3 systems M s = r (M (..., 3, 3), r (..., 3)) by Cramer's
+    rule: s_c = det(M with column c replaced by r) / det(M)."""
+    def det(A):
+        return (A[..., 0, 0] * (A[..., 1, 1] * A[..., 2, 2] - A[..., 1, 2] * A[..., 2, 1])
+                - A[..., 0, 1] * (A[..., 1, 0] * A[..., 2, 2] - A[..., 1, 2] * A[..., 2, 0])
+                + A[..., 0, 2] * (A[..., 1, 0] * A[..., 2, 1] - A[..., 1, 1] * A[..., 2, 0]))
+    d = det(M)
+    out = []
+    for c in range(3):
+        Mc = M.copy()
+        Mc[..., :, c] = r
+        out.append(det(Mc) / d)
+    return out
+
+
 def midpoint_rotation(state, hx, hy):
     """Solve s' = s + ((s + s') / 2) x b spin by spin, with b = (h^y dt, -h^x dt, 0)
     (so that s x b is the increment of Eq. (S1)): the implicit midpoint rule of
     ds = s x b with b held fixed, a 3 x 3 linear system per spin.  Writing
-    [b] for the matrix of b x ., it reads (I + [b]/2) s' = (I - [b]/2) s."""
+    [b] for the matrix of b x ., it reads (I + [b]/2) s' = (I - [b]/2) s,
+    solved by Cramer's rule (det(I + [b]/2) = 1 + |b|^2/4 > 0)."""
     x, y, z = state
     bx, by = hy, -hx
     B, n = x.shape
@@ -203,9 +220,9 @@ def midpoint_rotation(state, hx, hy):
     K[..., 2, 1] = bx
     eye = np.eye(3)
     s = np.stack([x, y, z], axis=-1)[..., None]
-    rhs = (eye - 0.5 * K) @ s
-    out = np.linalg.solve(eye + 0.5 * K, rhs)[..., 0]
-    return out[..., 0], out[..., 1], out[..., 2]
+    rhs = ((eye - 0.5 * K) @ s)[..., 0]
+    ox, oy, oz = _solve3(eye + 0.5 * K, rhs)
+    return ox, oy, oz
 
 
 def sib_step(state, W, gamma, dt, dxi, dchi):

@@ -125,3 +125,39 @@ def test_jackknife_se_of_mean_matches_block_standard_error():
     bm = x.reshape(32, 8, 5).mean(1)
     for j, name in enumerate(observables.MOMENT_NAMES):
         assert np.isclose(out[name + "_se"], bm[:, j].std(ddof=1) / np.sqrt(32), rtol=1e-10)
+
+
+def _paper_values(golden_dir):
+    import os
+    vals = {}
+    for line in open(os.path.join(golden_dir, "paper_values.txt")):
+        if line.strip() and not line.startswith("#"):
+            k, v = line.split()
+            vals[k] = float(v)
+    return vals
+
+
+def test_alpha0_w_equals_gamma_g2_tends_to_paper_six_fifths(golden_dir):
+    """The exact stationary TWA law at alpha = 0, w = Gamma approaches the
+    paper's printed g2 = 6/5 as N grows (1.2133, 1.2015, 1.2001 at N = 10, 40,
+    200), from above and monotonically; a dropped moment or a wrong
+    coefficient of Eq. (S2) moves the limit."""
+    target = _paper_values(golden_dir)["g2_collective_pump_w_equals_gamma"]
+    g = []
+    for n in (10, 40, 200):
+        g.append(observables.derived(closed_forms.stationary_alpha0(n, 1.0, 1.0))[2])
+    assert abs(g[0] - 1.2133) < 1e-4 and abs(g[1] - 1.2015) < 1e-4
+    assert abs(g[2] - target) < 2e-4
+    assert g[0] > g[1] > g[2] > target
+
+
+def test_alpha0_thermal_g2_tends_to_paper_two(golden_dir):
+    """For w != Gamma the paper's collective-pump steady state is thermal,
+    g2 -> 2 as N grows; the exact stationary TWA law reproduces that limit on
+    both sides of w = Gamma, with an O(1/N) offset."""
+    target = _paper_values(golden_dir)["g2_collective_pump_thermal"]
+    for w in (0.25, 4.0):
+        g = [observables.derived(closed_forms.stationary_alpha0(n, 1.0, w))[2] for n in (20, 80, 200)]
+        errs = [abs(x - target) for x in g]
+        assert errs[2] < 0.03, (w, g)
+        assert errs[0] > errs[1] > errs[2], (w, g)
