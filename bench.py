@@ -3,31 +3,44 @@
 
 Workload (the headline configuration): a chain of N = 10^4 atoms, pump
 exponent alpha = 1, w = ln(N) Gamma, Gamma = 1, 1024 trajectories, dt = 1e-4,
-2e4 stochastic Heun steps of Eq. (S1) with the averaging window over the last
-half, the channel-mixing contraction in BF16 on MFMA with FP32 accumulation
-and FP32 spin updates.  All inputs are synthetic: the Philox stream of the
-method, keyed by seed 0.
+the channel-mixing contraction in BF16 on MFMA with FP32 accumulation and FP32
+spin updates, integrated with the spin-length-preserving semi-implicit scheme
+the paper uses (the stochastic Heun scheme drifts |s|^2 by 0.47 at this step
+size and is reported beside it).  All inputs are synthetic: the Philox stream
+of the method, keyed by seed 0.
 
-One bench "step" is one complete ``twa_run`` of that workload (noise,
-contractions, Heun stages, observables); the pump factorisation is built once
+One bench "step" is 1000 integration steps of the whole hot path (noise,
+contractions, stage updates, collective sums, window observables) over the
+1024-trajectory batch.  ``--steps K`` times ONE ``twa_run`` of K * 1000
+integration steps (averaging window over its last half), so ``--steps 20``
+times exactly the 2e4-step headline run; ``--warmup W`` runs W * 1000
+untimed integration steps first.  The pump factorisation is built once
 before the timed region and reported separately.  ``value`` is
-trajectory-atom-steps/s = n_traj * N * n_steps / wall time per run.
+trajectory-atom-steps/s = n_traj * N * (K * 1000) / wall.
 
 The ``roofline`` object refers to the predictor contraction (the larger of the
 two contraction launches of a step): algorithmic flops per launch
 2 * N * (2N) * (2 n_traj), divided by its mean launch duration from HIP events
-recorded by the library on its stream during the timed runs.
+recorded by the library on its stream during the timed run.
 
-``cpu_baseline`` times the FP64 NumPy oracle (test infrastructure) on the
-host's cores on a bounded sample of the same workload (a few trajectories for
-a few steps at N = 10^4).
+Beside the headline (each skippable):
+  * ``heun``: the same run with the stochastic Heun integrator and the shift
+    of its observables against the semi-implicit run, in standard errors;
+  * ``precision``: the headline workload for 2000 steps in FP64, FP32, split
+    BF16 (hi + lo), BF16 and FP16: time per step, speed-up over FP32 and the
+    error of <S^z>, <S+S-> and g2 against FP64 (same noise);
+  * ``linewidth_precision``: the linewidth of the two-time correlation on the
+    N = 1000 workload in FP64, FP32, BF16 and FP16;
+  * ``toeplitz_path``: the headline workload through the circulant embedding
+    of Eq. (2), FP32;
+  * ``adjoint``: the second half of the metric, wall(twa_adjoint for
+    dg2/d(w, alpha)) / wall(twa_run) at N = 2000, 2048 trajectories, FP32;
+  * ``cpu_baseline``: the FP64 NumPy oracle (test infrastructure) on the host's
+    cores on a bounded sample of the headline workload (32 trajectories).
 
-``adjoint`` is the second half of the metric: the cost of the pathwise
-gradients d<S+S->/d(w, alpha) and dg2/d(w, alpha) (checkpointed forward plus
-reverse sweep) relative to a plain forward run of the same configuration
-(N = 2000, alpha = 1, w = 2, 2048 trajectories, dt = 1e-4, FP32 contractions,
-a checkpoint every 256 steps).  The ratio is per step, so a bounded number of
-steps (2048, i.e. 8 checkpoint segments) is timed.
+Profiling modes: ``--copy-calibration`` (one 1 GiB device copy, the scale of
+the FETCH_SIZE / WRITE_SIZE counters), ``--toeplitz-only`` (the Toeplitz
+kernel on the headline workload, 256 + 512 steps).
 """
 from __future__ import annotations
 
@@ -43,8 +56,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "trajectory-atom-steps/s at N=1e4 + adjoint d(g2)/d(w,alpha) cost vs forward"
-PEAK_TFLOPS = {"bf16": 2500.0, "fp16": 2500.0, "fp32": 157.3, "fp64": 78.6}
-KERNEL_SOURCES = ["paper_2608_10075_amd/csrc/twa_step.hip", "paper_2608_10075_amd/csrc/twa_device.h"]
+PEAK_TFLOPS = {"bf16": 2500.0, "fp16": 2500.0, "bf16x3": 2500.0, "fp32": 157.3, "fp64": 78.6}
+KERNEL_SOURCES = ["paper_2608_10075_amd/csrc/twa_step_impl.h", "paper_2608_10075_amd/csrc/twa_device.h"]
+STEPS_PER_BENCH_STEP = 1000
 
 
 def kernel_source_hash() -> str:
@@ -55,10 +69,10 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(workload: str, precision: str):
+def traffic_from_profiles(workload: str, precision: str, integrator: str):
     """HBM bytes per launch of the predictor contraction from the committed
     rocprofv3 counter summary, if it was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", "stage1_traffic_%s_%s.json" % (workload, precision))
+    path = os.path.join(ROOT, "profiles", "stage1_traffic_%s_%s_%s.json" % (workload, precision, integrator))
     if not os.path.exists(path):
         return None
     try:
@@ -70,15 +84,15 @@ def traffic_from_profiles(workload: str, precision: str):
     return d.get("bytes_per_launch")
 
 
-def cpu_baseline(N, w, alpha, dt, budget_s=15.0, threads=None, pump=None):
+def cpu_baseline(N, w, alpha, dt, integrator, budget_s=15.0, threads=None, pump=None, B=32):
     """The FP64 oracle as it stands, timed on a bounded sample of the workload
-    (BLAS threads: all, or limited to ``threads``).  ``pump`` = (oracle pump,
-    its build time) reuses an oracle pump built earlier (the one-time
-    eigendecomposition is not part of the rate); returns (line, pump)."""
+    (B trajectories, BLAS threads: all, or limited to ``threads``).  ``pump`` =
+    (oracle pump, its build time) reuses an oracle pump built earlier (the
+    one-time eigendecomposition is not part of the rate); returns (line, pump)."""
     if threads is not None:
         from threadpoolctl import threadpool_limits
         with threadpool_limits(limits=threads):
-            return cpu_baseline(N, w, alpha, dt, budget_s, pump=pump)
+            return cpu_baseline(N, w, alpha, dt, integrator, budget_s, pump=pump, B=B)
     from oracle import pump as opump, twa as otwa
     try:
         from threadpoolctl import threadpool_info
@@ -89,8 +103,7 @@ def cpu_baseline(N, w, alpha, dt, budget_s=15.0, threads=None, pump=None):
         t0 = time.time()
         pump = (opump.build_pump(N, w, alpha), time.time() - t0)
     p, build_s = pump
-    B = 4
-    cfg = otwa.RunConfig(n_spin=N, w=w, alpha=alpha, n_traj=B, dt=dt, n_steps=1, seed=0)
+    cfg = otwa.RunConfig(n_spin=N, w=w, alpha=alpha, n_traj=B, dt=dt, n_steps=1, seed=0, integrator=integrator)
     state = otwa.initial_state(0, B, N)
     t0 = time.time()
     state = otwa.run_steps(state, p, cfg, 0, 2)
@@ -101,30 +114,34 @@ def cpu_baseline(N, w, alpha, dt, budget_s=15.0, threads=None, pump=None):
     el = time.time() - t0
     return {"value": B * N * steps / el, "unit": "trajectory-atom-steps/s", "cores": int(cores),
             "kind": "oracle",
-            "sample": "FP64 NumPy oracle, N=%d, %d trajectories x %d Heun steps (%.1f s); pump eigendecomposition "
-                      "%.1f s (all cores) not included" % (N, B, steps, el, build_s)}, pump
+            "sample": "FP64 NumPy oracle (%s integrator), N=%d, %d trajectories x %d steps (%.1f s); pump "
+                      "eigendecomposition %.1f s not included" % (integrator, N, B, steps, el, build_s)}, pump
 
 
 def adjoint_cost(twa, steps=2048, reps=1):
     """Wall time of twa_adjoint (forward with checkpoints + reverse sweep) for
     dg2/d(w, alpha) divided by the wall time of twa_run on the same
-    configuration; also the cost with both objectives (<S+S-> and g2) swept."""
+    configuration; also the cost with both objectives (<S+S-> and g2) swept.
+    Heun (the adjoint's integrator) at dt = 1e-4 (step criterion 0.2) drifts
+    the spin lengths past the default check, so the check is off here and the
+    drift is reported."""
     import torch
     N, B, w, alpha, dt, ck = 2000, 2048, 2.0, 1.0, 1e-4, 256
     pump = twa.build_pump(N, w, alpha)
-    twa.run(pump, B, dt, 64, seed=0, precision="fp32")           # warm caches / graphs
-    twa.adjoint(pump, B, dt, 256, seed=0, precision="fp32", ckpt_every=ck, objectives=("g2",))
+    twa.run(pump, B, dt, 64, seed=0, precision="fp32", norm_tol=-1)           # warm caches / graphs
+    twa.adjoint(pump, B, dt, 256, seed=0, precision="fp32", ckpt_every=ck, objectives=("g2",), norm_tol=-1)
     fwd, adj, adj2 = [], [], []
     for _ in range(reps):
         torch.cuda.synchronize()
         t0 = time.time()
-        r = twa.run(pump, B, dt, steps, seed=0, precision="fp32")
+        r = twa.run(pump, B, dt, steps, seed=0, precision="fp32", norm_tol=-1)
         torch.cuda.synchronize()
         t1 = time.time()
-        obs, grads = twa.adjoint(pump, B, dt, steps, seed=0, precision="fp32", ckpt_every=ck, objectives=("g2",))
+        obs, grads = twa.adjoint(pump, B, dt, steps, seed=0, precision="fp32", ckpt_every=ck, objectives=("g2",),
+                                 norm_tol=-1)
         torch.cuda.synchronize()
         t2 = time.time()
-        twa.adjoint(pump, B, dt, steps, seed=0, precision="fp32", ckpt_every=ck)
+        twa.adjoint(pump, B, dt, steps, seed=0, precision="fp32", ckpt_every=ck, norm_tol=-1)
         torch.cuda.synchronize()
         t3 = time.time()
         fwd.append(t1 - t0)
@@ -135,9 +152,9 @@ def adjoint_cost(twa, steps=2048, reps=1):
     return {"ratio": a / f, "forward_s": f, "adjoint_s": a, "steps": steps, "objective": "g2",
             "ratio_both_objectives": a2 / f,
             "config": {"N": N, "alpha": alpha, "w": w, "n_traj": B, "dt": dt, "precision": "fp32",
-                       "ckpt_every": ck, "tile_config": r.obs["tile_config"]},
+                       "ckpt_every": ck, "tile_config": r.obs["tile_config"], "integrator": "heun"},
             "forward_ms_per_step": 1e3 * f / steps, "adjoint_ms_per_step": 1e3 * a / steps,
-            "gradients": grads}
+            "max_norm_dev": obs["max_norm_dev"], "gradients": grads}
 
 
 def scan_points(n_points=96, seed=0):
@@ -162,7 +179,7 @@ def scan_points(n_points=96, seed=0):
     return pts
 
 
-def batch_scan(twa, steps):
+def batch_scan(twa, steps, integrator="sib", singles=True):
     """Batched scan (grouped persistent launches, graph replay, autotuned
     tiles) against the same 96 points run one by one through the plain FP32
     path, and one by one through the Toeplitz path; device time of the step
@@ -171,29 +188,107 @@ def batch_scan(twa, steps):
     pts = scan_points()
     B = 512
     t0 = time.time()
-    res = twa.run_batch(pts, B, steps, precision="fp32")
+    res = twa.run_batch(pts, B, steps, precision="fp32", integrator=integrator,
+                        progress=max(1000, steps // 20))
     torch.cuda.synchronize()
     batch_wall = time.time() - t0
     batch_ms = res[0]["kernel_ms"]
-    single_ms = 0.0
-    toep_ms = 0.0
-    for i, (N, w, a, dt, seed) in enumerate(pts):
-        p = twa.build_pump(N, w, a)
-        r = twa.run(p, B, dt, steps, seed=seed, point=i, precision="fp32")
-        single_ms += r.obs["kernel_ms"]
-        p.close()
-        lt = twa.build_pump_toeplitz(N, w, a)
-        t = twa.run(lt, B, dt, steps, seed=seed, point=i, precision="fp32", pump_path="toeplitz")
-        toep_ms += t.obs["kernel_ms"]
     work = sum(B * N * steps for (N, _, _, _, _) in pts)
+    flops = sum(12.0 * N * N * B * steps for (N, _, _, _, _) in pts)
     crit = [r["step_criterion"] for r in res]
-    return {"points": len(pts), "n_traj": B, "steps": steps, "precision": "fp32",
-            "N_list": [p[0] for p in pts], "step_criterion_min_max": [min(crit), max(crit)],
-            "batched_ms": batch_ms, "single_runs_ms": single_ms, "toeplitz_single_runs_ms": toep_ms,
-            "speedup_batched_vs_single": single_ms / batch_ms,
-            "speedup_toeplitz_vs_single": single_ms / toep_ms,
-            "batched_rate": work / (batch_ms * 1e-3), "unit": "trajectory-atom-steps/s",
-            "batch_wall_s_incl_pumps_and_tuning": batch_wall}
+    out = {"points": len(pts), "n_traj": B, "steps": steps, "precision": "fp32", "integrator": integrator,
+           "N_list": [p[0] for p in pts], "step_criterion_min_max": [min(crit), max(crit)],
+           "tile_configs": sorted(set(r["tile_config"] for r in res)),
+           "batched_ms": batch_ms, "batched_rate": work / (batch_ms * 1e-3), "unit": "trajectory-atom-steps/s",
+           "batched_tflops": flops / (batch_ms * 1e-3) / 1e12,
+           "batched_frac_fp32_peak": flops / (batch_ms * 1e-3) / 1e12 / PEAK_TFLOPS["fp32"],
+           "batch_wall_s_incl_pumps_and_tuning": batch_wall,
+           "max_norm_dev_max": max(r["max_norm_dev"] for r in res)}
+    if singles:
+        single_ms = 0.0
+        toep_ms = 0.0
+        for i, (N, w, a, dt, seed) in enumerate(pts):
+            p = twa.build_pump(N, w, a)
+            r = twa.run(p, B, dt, steps, seed=seed, point=i, precision="fp32", integrator=integrator)
+            single_ms += r.obs["kernel_ms"]
+            p.close()
+            lt = twa.build_pump_toeplitz(N, w, a)
+            t = twa.run(lt, B, dt, steps, seed=seed, point=i, precision="fp32", pump_path="toeplitz", norm_tol=-1)
+            toep_ms += t.obs["kernel_ms"]
+        out.update({"single_runs_ms": single_ms, "toeplitz_single_runs_ms": toep_ms,
+                    "speedup_batched_vs_single": single_ms / batch_ms,
+                    "speedup_toeplitz_vs_single": single_ms / toep_ms})
+    return out
+
+
+def _se_shift(a, b, k):
+    """difference of observable k between two runs in combined standard errors"""
+    return (a[k] - b[k]) / math.sqrt(a[k + "_se"] ** 2 + b[k + "_se"] ** 2)
+
+
+def heun_line(twa, pump, B, dt, T, prec, sib_obs):
+    """The headline run with the stochastic Heun integrator (no spin-length
+    check: its drift at this step size is the point of the comparison)."""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.time()
+    r = twa.run(pump, B, dt, T, seed=0, precision=prec, integrator="heun", norm_tol=-1)
+    torch.cuda.synchronize()
+    wall = time.time() - t0
+    o = r.obs
+    return {"value": B * pump.N * T / wall, "unit": "trajectory-atom-steps/s", "n_steps": T,
+            "ms_per_integration_step": o["kernel_ms"] / T, "max_norm_dev": o["max_norm_dev"],
+            "observables": {k: o[k] for k in ("Sz", "SpSm", "g2", "Sz_se", "SpSm_se", "g2_se")},
+            "shift_vs_semi_implicit_in_se": {k: _se_shift(o, sib_obs, k) for k in ("Sz", "SpSm", "g2")},
+            "relative_shift_vs_semi_implicit": {k: (o[k] - sib_obs[k]) / abs(sib_obs[k]) for k in ("SpSm", "g2")}}
+
+
+def precision_table(twa, pump, B, dt, integrator, T=2000):
+    """The headline workload for T steps (window over the last half, same
+    noise) in every contraction precision: device time per step, speed-up
+    over FP32, and the error of <S^z>, <S+S-> and g2 against FP64 (relative,
+    and in units of the FP64 run's standard error)."""
+    out = {"n_steps": T, "integrator": integrator, "modes": {}}
+    runs = {}
+    for prec in ("fp64", "fp32", "bf16x3", "bf16", "fp16"):
+        print("[bench]   precision %s, %d steps" % (prec, T), file=sys.stderr, flush=True)
+        twa.run(pump, B, dt, 16, seed=0, precision=prec, integrator=integrator, norm_tol=-1)
+        r = twa.run(pump, B, dt, T, seed=0, precision=prec, integrator=integrator, norm_tol=-1)
+        runs[prec] = r.obs
+    ref = runs["fp64"]
+    for prec, o in runs.items():
+        m = {"ms_per_step": o["kernel_ms"] / T, "speedup_vs_fp32": runs["fp32"]["kernel_ms"] / o["kernel_ms"],
+             "tile_config": o["tile_config"], "max_norm_dev": o["max_norm_dev"]}
+        if prec != "fp64":
+            m["rel_error_vs_fp64"] = {k: abs(o[k] - ref[k]) / abs(ref[k]) for k in ("Sz", "SpSm", "g2")}
+            m["error_vs_fp64_in_se"] = {k: abs(o[k] - ref[k]) / ref[k + "_se"] for k in ("Sz", "SpSm", "g2")}
+        else:
+            m["observables"] = {k: o[k] for k in ("Sz", "SpSm", "g2", "Sz_se", "SpSm_se", "g2_se")}
+        out["modes"][prec] = m
+    return out
+
+
+def linewidth_precision(twa, N=1000, w=1.0, alpha=1.0, B=1024, dt=1e-4, T=4000, lags=500):
+    """Linewidth (FWHM of the spectrum of the two-time correlation, from the two
+    tangent-linear response copies) of the N = 1000 workload in FP64, FP32,
+    BF16 and FP16 contractions, same noise, and its error against FP64; Heun
+    (the response copies are defined for it), window over the last half."""
+    pump = twa.build_pump(N, w, alpha)
+    burn = T // 2
+    stride = max(1, (T - burn) // lags)
+    out = {"config": {"N": N, "w": w, "alpha": alpha, "n_traj": B, "dt": dt, "n_steps": T, "burnin": burn,
+                      "n_lags": lags, "lag_stride": stride}, "modes": {}}
+    res = {}
+    for prec in ("fp64", "fp32", "bf16", "fp16"):
+        r = twa.run(pump, B, dt, T, seed=0, precision=prec, burnin=burn, n_lags=lags, lag_stride=stride, norm_tol=-1)
+        res[prec] = r.obs
+    ref = res["fp64"]
+    for prec, o in res.items():
+        out["modes"][prec] = {"linewidth": o["linewidth"], "linewidth_sym": o["linewidth_sym"],
+                              "ms_per_step": o["kernel_ms"] / T,
+                              "rel_error_vs_fp64": abs(o["linewidth"] - ref["linewidth"]) / abs(ref["linewidth"]),
+                              "max_norm_dev": o["max_norm_dev"]}
+    return out
 
 
 def sib_rate(twa, pump, B, dt, prec, steps=400):
@@ -201,8 +296,8 @@ def sib_rate(twa, pump, B, dt, prec, steps=400):
     on the headline pump (same three operand sweeps per step)."""
     out = {}
     for integ in ("heun", "sib"):
-        twa.run(pump, B, dt, 32, seed=0, precision=prec, integrator=integ)
-        r = twa.run(pump, B, dt, steps, seed=0, precision=prec, integrator=integ)
+        twa.run(pump, B, dt, 32, seed=0, precision=prec, integrator=integ, norm_tol=-1)
+        r = twa.run(pump, B, dt, steps, seed=0, precision=prec, integrator=integ, norm_tol=-1)
         out[integ + "_ms_per_step"] = r.obs["kernel_ms"] / steps
         out[integ + "_max_norm_dev"] = r.obs["max_norm_dev"]
     out["steps"] = steps
@@ -219,10 +314,10 @@ def two_time_cost(twa, N=1000, w=1.0, alpha=1.0, B=4096, dt=1e-4, T=4000, lags=5
     pump = twa.build_pump(N, w, alpha)
     burn = T // 2
     stride = max(1, (T - burn) // lags)
-    twa.run(pump, B, dt, 64, seed=0, precision=prec)
-    plain = twa.run(pump, B, dt, T, seed=0, precision=prec, burnin=burn).obs["kernel_ms"]
-    twa.run(pump, B, dt, 64, seed=0, precision=prec, burnin=32, n_lags=16, lag_stride=2)
-    r = twa.run(pump, B, dt, T, seed=0, precision=prec, burnin=burn, n_lags=lags, lag_stride=stride)
+    twa.run(pump, B, dt, 64, seed=0, precision=prec, norm_tol=-1)
+    plain = twa.run(pump, B, dt, T, seed=0, precision=prec, burnin=burn, norm_tol=-1).obs["kernel_ms"]
+    twa.run(pump, B, dt, 64, seed=0, precision=prec, burnin=32, n_lags=16, lag_stride=2, norm_tol=-1)
+    r = twa.run(pump, B, dt, T, seed=0, precision=prec, burnin=burn, n_lags=lags, lag_stride=stride, norm_tol=-1)
     lagged = r.obs["kernel_ms"]
     per_step = plain / T
     window = (lagged - plain) / (T - burn) + per_step
@@ -234,7 +329,7 @@ def two_time_cost(twa, N=1000, w=1.0, alpha=1.0, B=4096, dt=1e-4, T=4000, lags=5
 
 
 def threshold_vs_scan(twa, N=2000, alpha=1.0, B=2048, dt=1e-4, T=2048):
-    """Locating a threshold by Newton steps with adjoint gradients against
+    """Locating a threshold by Newton steps with pathwise gradients against
     forward-only searches, at fixed noise: <S+S->/N = target on a bracket
     found by a coarse scan (target 1, the paper's criterion, when the scan
     crosses it), FP32, tolerance 1e-6 relative in w."""
@@ -247,7 +342,7 @@ def threshold_vs_scan(twa, N=2000, alpha=1.0, B=2048, dt=1e-4, T=2048):
         p = twa.build_pump(N, float(w), alpha)
         torch.cuda.synchronize()
         t0 = time.time()
-        r = twa.run(p, B, dt, T, seed=0, precision="fp32", burnin=burn)
+        r = twa.run(p, B, dt, T, seed=0, precision="fp32", burnin=burn, norm_tol=-1)
         torch.cuda.synchronize()
         t_fwd.append(time.time() - t0)
         vals.append(r.obs["SpSm"] / N)
@@ -261,74 +356,128 @@ def threshold_vs_scan(twa, N=2000, alpha=1.0, B=2048, dt=1e-4, T=2048):
         target = 0.5 * (vals[i] + vals[i + 1])
     lo, hi = float(grid[i]), float(grid[i + 1])
     tol = 1e-6 * hi
-    torch.cuda.synchronize()
-    t0 = time.time()
-    w_root, f_root, it = twa.find_threshold(N, alpha, B, dt, T, 0, objective="spsm_n", target=target, w_lo=lo,
-                                            w_hi=hi, tol_w=tol, precision="fp32", burnin=burn)
-    torch.cuda.synchronize()
-    newton_s = time.time() - t0
     fwd = float(np.median(t_fwd))
     n_bisect = int(math.ceil(math.log2((hi - lo) / tol)))
-    return {"config": {"N": N, "alpha": alpha, "n_traj": B, "dt": dt, "n_steps": T, "precision": "fp32"},
-            "objective": "spsm_n", "target": target, "bracket": [lo, hi], "w_root": w_root, "residual": f_root,
-            "gradient_evaluations": it, "newton_s": newton_s, "forward_run_s": fwd,
-            "bisection_forward_runs_same_tol": n_bisect,
-            "speedup_vs_bisection": n_bisect * fwd / newton_s,
-            "uniform_scan_points_same_time": int(newton_s / fwd),
-            "uniform_scan_resolution_same_time": (hi - lo) / max(1, int(newton_s / fwd))}
+    out = {"config": {"N": N, "alpha": alpha, "n_traj": B, "dt": dt, "n_steps": T, "precision": "fp32"},
+           "objective": "spsm_n", "target": target, "bracket": [lo, hi], "forward_run_s": fwd,
+           "bisection_forward_runs_same_tol": n_bisect}
+    for mode in ("forward", "adjoint"):
+        torch.cuda.synchronize()
+        t0 = time.time()
+        w_root, f_root, it = twa.find_threshold(N, alpha, B, dt, T, 0, objective="spsm_n", target=target, w_lo=lo,
+                                                w_hi=hi, tol_w=tol, precision="fp32", burnin=burn, norm_tol=-1,
+                                                derivative=mode)
+        torch.cuda.synchronize()
+        el = time.time() - t0
+        out[mode] = {"w_root": w_root, "residual": f_root, "gradient_evaluations": it, "newton_s": el,
+                     "speedup_vs_bisection": n_bisect * fwd / el}
+    return out
 
 
 def toeplitz_rate(twa, N, w, alpha, B, dt, T, dense_value):
     """The same workload through the circulant embedding of Eq. (2) (FFT
-    drift and circulant pump noise, equal in law to the dense path), FP32,
-    one full run after a short warm-up run."""
+    drift and circulant pump noise, equal in law to the dense path), FP32
+    Heun (its only integrator; no spin-length check), one full run after a
+    short warm-up run."""
     import torch
     light = twa.build_pump_toeplitz(N, w, alpha)
-    twa.run(light, B, dt, 256, seed=0, precision="fp32", pump_path="toeplitz")
+    twa.run(light, B, dt, 256, seed=0, precision="fp32", pump_path="toeplitz", norm_tol=-1)
     torch.cuda.synchronize()
     t0 = time.time()
-    r = twa.run(light, B, dt, T, seed=0, precision="fp32", pump_path="toeplitz")
+    r = twa.run(light, B, dt, T, seed=0, precision="fp32", pump_path="toeplitz", norm_tol=-1)
     torch.cuda.synchronize()
     wall = time.time() - t0
     value = B * N * T / wall
     M = 256
     while M < 2 * N - 2:
         M *= 2
-    return {"value": value, "unit": "trajectory-atom-steps/s", "precision": "fp32", "wall_s": wall,
-            "kernel_ms": r.obs["kernel_ms"], "speedup_vs_dense": value / dense_value, "embedding_size": M,
+    return {"value": value, "unit": "trajectory-atom-steps/s", "precision": "fp32", "integrator": "heun",
+            "n_steps": T, "wall_s": wall, "kernel_ms": r.obs["kernel_ms"], "speedup_vs_dense": value / dense_value,
+            "embedding_size": M, "max_norm_dev": r.obs["max_norm_dev"],
             "observables": {k: r.obs[k] for k in ("Sz", "SpSm", "g2", "Sz_se", "SpSm_se", "g2_se")}}
+
+
+def copy_calibration():
+    """One plain device copy of a known size (1 GiB read, 1 GiB written), run
+    under rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE to obtain the scale between
+    counter readings and bytes moved."""
+    import torch
+    n = 1 << 28                      # 2^28 float32 = 1 GiB
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    y.copy_(x)
+    torch.cuda.synchronize()
+    print("copied %d bytes" % (4 * n), flush=True)
+
+
+def toeplitz_only(twa, N, w, alpha, B, dt):
+    """Profiling workload of the Toeplitz kernel: a one-launch warm-up run of
+    256 steps, then 512 steps (two launches of 256)."""
+    import torch
+    p = twa.build_pump_toeplitz(N, w, alpha)
+    twa.run(p, B, dt, 256, seed=0, precision="fp32", pump_path="toeplitz", norm_tol=-1)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    r = twa.run(p, B, dt, 512, seed=0, precision="fp32", pump_path="toeplitz", norm_tol=-1)
+    torch.cuda.synchronize()
+    print("toeplitz N=%d B=%d: %.3f ms per step (kernel %.3f)" % (N, B, 1e3 * (time.time() - t0) / 512,
+                                                                 r.obs["kernel_ms"] / 512), flush=True)
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20, help="bench steps of 1000 integration steps each")
+    ap.add_argument("--warmup", type=int, default=1, help="untimed bench steps before the timed run")
     ap.add_argument("--precision", default="bf16", choices=sorted(PEAK_TFLOPS))
+    ap.add_argument("--integrator", default="sib", choices=["sib", "heun"])
     ap.add_argument("--tile-config", type=int, default=-1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-toeplitz", action="store_true")
-    ap.add_argument("--sib", action="store_true", help="also time the semi-implicit scheme against Heun")
+    ap.add_argument("--no-heun", action="store_true")
+    ap.add_argument("--no-precision", action="store_true")
+    ap.add_argument("--no-linewidth", action="store_true")
+    ap.add_argument("--headline-only", action="store_true", help="skip every line beside the headline")
+    ap.add_argument("--sib", action="store_true", help="also time the semi-implicit scheme against Heun per step")
     ap.add_argument("--threshold", action="store_true",
-                    help="also time a Newton threshold search against forward-only searches")
+                    help="also time the Newton threshold searches against bisection")
     ap.add_argument("--two-time", action="store_true",
                     help="also time the two-time correlation window (N = 1000, 4096 trajectories, FP32)")
     ap.add_argument("--batch-scan", type=int, default=0,
-                    help="also time the 96-point scan for this many steps (batched vs single runs)")
+                    help="also time the 96-point scan for this many steps")
+    ap.add_argument("--batch-singles", action="store_true",
+                    help="with --batch-scan: also run the 96 points one by one (dense and Toeplitz)")
+    ap.add_argument("--copy-calibration", action="store_true", help="one 1 GiB device copy, then exit")
+    ap.add_argument("--toeplitz-only", action="store_true", help="the Toeplitz profiling workload, then exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path (trajectories would shard "
               "across GPUs with one all-reduce of the accumulators at the end)", file=sys.stderr)
         sys.exit(2)
+    if args.steps < 1 or args.warmup < 0:
+        print("--steps must be >= 1 and --warmup >= 0", file=sys.stderr)
+        sys.exit(2)
 
     import torch
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        copy_calibration()
+        return
     import paper_2608_10075_amd as twa
 
-    N, alpha, B, dt, T = 10000, 1.0, 1024, 1e-4, 20000
+    N, alpha, B, dt = 10000, 1.0, 1024, 1e-4
+    T = STEPS_PER_BENCH_STEP * args.steps
     w = math.log(N)
     prec = args.precision
+    integ = args.integrator
+    if args.toeplitz_only:
+        toeplitz_only(twa, N, w, alpha, B, dt)
+        return
+    if args.headline_only:
+        args.no_cpu_baseline = args.no_adjoint = args.no_toeplitz = args.no_heun = True
+        args.no_precision = args.no_linewidth = True
     workload = "n1e4"
     print("[bench] building pump N=%d alpha=%g w=%.4f" % (N, alpha, w), file=sys.stderr, flush=True)
     t0 = time.time()
@@ -336,33 +485,29 @@ def main():
     torch.cuda.synchronize()
     pump_s = time.time() - t0
 
-    def one(timing):
-        return twa.run(pump, B, dt, T, seed=0, precision=prec, tile_config=args.tile_config, timing=timing)
-
-    for i in range(args.warmup):
-        print("[bench] warmup run %d/%d" % (i + 1, args.warmup), file=sys.stderr, flush=True)
-        one(True)
+    if args.warmup > 0:
+        print("[bench] warmup: %d integration steps" % (STEPS_PER_BENCH_STEP * args.warmup), file=sys.stderr,
+              flush=True)
+        twa.run(pump, B, dt, STEPS_PER_BENCH_STEP * args.warmup, seed=0, precision=prec, integrator=integ,
+                tile_config=args.tile_config, timing=True)
+    print("[bench] timed run: %d integration steps (%d bench steps)" % (T, args.steps), file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.time()
-    results = []
-    for i in range(args.steps):
-        print("[bench] timed run %d/%d" % (i + 1, args.steps), file=sys.stderr, flush=True)
-        results.append(one(True))
+    res = twa.run(pump, B, dt, T, seed=0, precision=prec, integrator=integ, tile_config=args.tile_config,
+                  timing=True, allow_unstable=(integ == "heun"))
     torch.cuda.synchronize()
     wall = time.time() - t0
+    print("[bench] timed run done: %.2f s" % wall, file=sys.stderr, flush=True)
     ms_per_step = 1e3 * wall / args.steps
-    value = B * N * T * args.steps / wall
-
-    s1_ms = sum(r.obs["stage1_ms"] for r in results)
-    s1_n = sum(r.obs["stage1_launches"] for r in results)
-    s2_ms = sum(r.obs["stage2_ms"] for r in results)
-    s2_n = sum(r.obs["stage2_launches"] for r in results)
+    value = B * N * T / wall
+    o = res.obs
     flops1 = 2.0 * N * (2 * N) * (2 * B)
     flops2 = 2.0 * N * N * (2 * B)
-    ach1 = flops1 / (s1_ms / s1_n * 1e-3) / 1e12
-    ach2 = flops2 / (s2_ms / s2_n * 1e-3) / 1e12
+    s1 = o["stage1_ms"] / o["stage1_launches"]
+    s2 = o["stage2_ms"] / o["stage2_launches"]
+    ach1 = flops1 / (s1 * 1e-3) / 1e12
+    ach2 = flops2 / (s2 * 1e-3) / 1e12
     peak = PEAK_TFLOPS[prec]
-    obs = results[-1].obs
     line = {
         "metric": METRIC,
         "value": value,
@@ -376,21 +521,34 @@ def main():
         "vs_baseline": None,
         "dtype": prec,
         "data": "synthetic",
-        "config": {"workload": "TWA chain N=10000 alpha=1 w=ln(N) Gamma=1, 1024 trajectories, dt=1e-4, %d Heun "
-                               "steps, window = last half, %s channel-mixing contraction" % (T, prec),
-                   "N": N, "alpha": alpha, "w": w, "n_traj": B, "dt": dt, "n_steps": T, "precision": prec,
-                   "parallelism": "single GPU"},
+        "config": {"workload": "TWA chain N=10000 alpha=1 w=ln(N) Gamma=1, 1024 trajectories, dt=1e-4, %d %s "
+                               "steps (one bench step = %d integration steps), window = last half, %s "
+                               "channel-mixing contraction" % (T, integ, STEPS_PER_BENCH_STEP, prec),
+                   "N": N, "alpha": alpha, "w": w, "n_traj": B, "dt": dt, "n_steps": T,
+                   "integration_steps_per_bench_step": STEPS_PER_BENCH_STEP, "precision": prec,
+                   "integrator": integ, "parallelism": "single GPU"},
         "roofline": {"bound": "mfma", "achieved": ach1, "peak": peak, "unit": "TFLOP/s", "frac": ach1 / peak,
-                     "traffic": traffic_from_profiles(workload, prec),
+                     "traffic": traffic_from_profiles(workload, prec, integ),
                      "kernel": "heun_stage_kernel stage 1 (predictor contraction, K = 2N)",
-                     "flops_per_launch": flops1, "mean_launch_ms": s1_ms / s1_n},
+                     "flops_per_launch": flops1, "mean_launch_ms": s1, "launches": o["stage1_launches"]},
         "roofline_stage2": {"achieved": ach2, "peak": peak, "unit": "TFLOP/s", "frac": ach2 / peak,
-                            "mean_launch_ms": s2_ms / s2_n, "flops_per_launch": flops2},
+                            "mean_launch_ms": s2, "flops_per_launch": flops2, "launches": o["stage2_launches"]},
+        "step_ms": o["kernel_ms"] / T,
         "pump_build_s": pump_s,
-        "observables": {k: obs[k] for k in ("Sz", "SpSm", "g2", "Sz_se", "SpSm_se", "g2_se", "max_norm_dev",
-                                             "step_criterion")},
-        "tile_config": obs["tile_config"],
+        "status": res.status,
+        "observables": {k: o[k] for k in ("Sz", "SpSm", "g2", "Sz_se", "SpSm_se", "g2_se", "max_norm_dev",
+                                          "step_criterion")},
+        "tile_config": o["tile_config"],
     }
+    if not args.no_heun and integ == "sib":
+        print("[bench] Heun integrator on the same workload", file=sys.stderr, flush=True)
+        line["heun"] = heun_line(twa, pump, B, dt, T, prec, o)
+    if not args.no_precision:
+        print("[bench] precision modes vs FP64 (2000 steps)", file=sys.stderr, flush=True)
+        line["precision"] = precision_table(twa, pump, B, dt, integ)
+    if not args.no_linewidth:
+        print("[bench] linewidth in each precision (N=1000)", file=sys.stderr, flush=True)
+        line["linewidth_precision"] = linewidth_precision(twa)
     if not args.no_toeplitz:
         print("[bench] Toeplitz fast path on the same workload (FP32)", file=sys.stderr, flush=True)
         line["toeplitz_path"] = toeplitz_rate(twa, N, w, alpha, B, dt, T, value)
@@ -405,14 +563,15 @@ def main():
         line["two_time"] = two_time_cost(twa)
     if args.batch_scan > 0:
         print("[bench] batched scan, 96 points, %d steps" % args.batch_scan, file=sys.stderr, flush=True)
-        line["batch_scan"] = batch_scan(twa, args.batch_scan)
+        line["batch_scan"] = batch_scan(twa, args.batch_scan, singles=args.batch_singles)
     if not args.no_adjoint:
         print("[bench] adjoint cost ratio (N=2000, FP32)", file=sys.stderr, flush=True)
         line["adjoint"] = adjoint_cost(twa)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
-        line["cpu_baseline"], opump_ = cpu_baseline(N, w, alpha, dt)
-        line["cpu_baseline_single_core"], _ = cpu_baseline(N, w, alpha, dt, budget_s=8.0, threads=1, pump=opump_)
+        line["cpu_baseline"], opump_ = cpu_baseline(N, w, alpha, dt, integ)
+        line["cpu_baseline_single_core"], _ = cpu_baseline(N, w, alpha, dt, integ, budget_s=8.0, threads=1,
+                                                           pump=opump_, B=8)
     print(json.dumps(line), flush=True)
 
 

@@ -49,8 +49,11 @@ extern "C" {
 #define TWA_ENOTPSD    -4   /* pump matrix has a negative eigenvalue below     */
                             /* -1e-10 * lambda_max (Eq. (2) is PSD; this flags */
                             /* a non-PSD dense matrix)                         */
-#define TWA_EUNSTABLE  -5   /* NaN/Inf in the state or accumulators; outputs   */
-                            /* are still written so they can be inspected      */
+#define TWA_EUNSTABLE  -5   /* NaN/Inf in the state or accumulators, or a spin */
+                            /* length that drifted: max_norm_dev above the    */
+                            /* run's norm_tol (Eq. (S1) keeps every |s_i|^2,  */
+                            /* SM Sec. S1).  Outputs are still written so     */
+                            /* they can be inspected                          */
 #define TWA_ENOROOT    -6   /* threshold search: the objective does not cross  */
                             /* the target on the bracket, or no convergence    */
 
@@ -212,11 +215,19 @@ typedef struct twa_params {
                              /* both.  The reverse sweep carries one copy per       */
                              /* objective; unselected gradients are returned NaN   */
     int32_t pump_path;       /* twa_run: TWA_PUMP_DENSE (default) or TWA_PUMP_TOEPLITZ */
+    double norm_tol;         /* spin-length check: Eq. (S1) conserves |s_i|^2, so a */
+                             /* run whose max_norm_dev exceeds norm_tol returns     */
+                             /* TWA_EUNSTABLE (outputs written).  0 = the default  */
+                             /* 1e-2; < 0 = no check (NaN/Inf are always flagged). */
+                             /* The stochastic Heun integrator drifts at first     */
+                             /* order in dt; the semi-implicit one keeps lengths  */
+                             /* to rounding                                        */
 } twa_params;
 
 /* Fills *p with defaults: gamma 1, s0z +1, burnin -1, Heun, FP32, no lags,
  * point 0, automatic tiles, null stream, no initial state, no per-launch
- * timing, hipGraph replay on, kappa 1/4, both adjoint objectives. */
+ * timing, hipGraph replay on, kappa 1/4, both adjoint objectives, dense
+ * pump path, norm_tol 1e-2. */
 TWA_API void twa_params_default(twa_params* p);
 
 typedef struct twa_observables {
@@ -323,22 +334,49 @@ typedef struct twa_batch_opts {
     int64_t burnin;          /* < 0: n_steps / 2                                  */
     double gamma;
     double s0z;
-    int32_t precision;       /* TWA_PREC_FP32 / BF16 / FP16                      */
-    int32_t use_graph;       /* capture the step loop in a hipGraph (default 1)  */
+    int32_t precision;       /* TWA_PREC_FP64 / FP32 / BF16 / FP16               */
+    int32_t use_graph;       /* capture the step loop in hipGraphs (default 1)   */
     int32_t steps_per_graph; /* steps captured per graph replay (<= 0: 16)       */
     const char* tune_cache;  /* autotuner cache file (NULL: no cache)            */
     void* stream;            /* hipStream_t                                      */
     int32_t integrator;      /* TWA_INT_HEUN (default) or TWA_INT_SIB            */
+    double norm_tol;         /* as twa_params.norm_tol, per point (0: 1e-2)      */
+    int64_t n_lags;          /* two-time lags per point, as twa_params (0: none; */
+                             /* Heun only)                                       */
+    int64_t lag_stride;      /* as twa_params                                    */
+    double kappa;            /* as twa_params (default 1/4)                      */
+    int32_t tile_config;     /* < 0: autotuned per N bucket; >= 0: one tile      */
+                             /* configuration (0..3, or 7 without FP64) for all  */
+    int64_t progress_every;  /* > 0: print a progress line to stderr every this  */
+                             /* many steps (the host then waits for the device   */
+                             /* at those steps); 0: silent                       */
+    const twa_outputs* outputs; /* host, optional: array of n_points twa_outputs */
+                             /* (traj_moments, final_state, corr_blocks,         */
+                             /* chi_blocks, n_blocks; traj_gen is not used)      */
 } twa_batch_opts;
 
+/* Defaults: 512 trajectories, 1000 steps, burn-in n_steps/2, gamma 1, s0z +1,
+ * FP32, graphs of 16 steps, no cache, null stream, Heun, norm_tol 1e-2, no
+ * lags, kappa 1/4, autotuned tiles, silent, no per-point arrays. */
 TWA_API void twa_batch_opts_default(twa_batch_opts* o);
 
 /*
- * twa_run_batch -- runs every point of `pts` (each with its own pump built
- * internally, Philox point index = position in `pts`) in grouped persistent
- * launches: every step of every point advances in the same launches, with
- * the work of all points in one LPT-ordered tile list.  outs[i] receives
- * point i's observables.  Errors as twa_run.
+ * twa_run_batch -- an uneven phase-diagram scan (main text, results: the
+ * (w~, alpha) diagrams and the N dependence): every point of `pts` is a full
+ * ensemble of Eq. (S1) trajectories with its own pump of Eq. (2) (built
+ * internally), its own step size and seed, and Philox point index = its
+ * position in `pts`; all points share n_traj, n_steps, the window and the
+ * lags.  The points are split into N buckets (N <= 128, N <= 1024, larger);
+ * every bucket advances in grouped persistent launches (one per stage and
+ * step, over the LPT-ordered tiles of all its points) with the tile
+ * configuration the autotuner measured fastest for it (cached on disk when a
+ * cache file is given), each bucket on its own stream branch of one captured
+ * hipGraph per steps_per_graph steps.  With n_lags > 0 every point also
+ * carries the two response copies of its two-time correlation and reports its
+ * linewidth.  Results equal those of twa_run on each point with the same tile
+ * configuration, bit for bit.  outs[i] receives point i's observables.
+ * Errors as twa_run; TWA_EUNSTABLE if any point is unstable (all outputs
+ * written).
  */
 TWA_API int twa_run_batch(const twa_point* pts, int n_points, const twa_batch_opts* o,
                           twa_observables* outs);
@@ -360,6 +398,23 @@ TWA_API int twa_run_batch(const twa_point* pts, int n_points, const twa_batch_op
 TWA_API int twa_adjoint(const twa_params* p, int64_t n_traj, double dt, int64_t n_steps,
                         uint64_t seed, int32_t ckpt_every, twa_observables* out,
                         double* grads);
+
+/*
+ * twa_tangent_w -- forward-mode counterpart of twa_adjoint for the pump
+ * amplitude w alone: the pathwise derivatives, at the fixed Philox stream,
+ *   grads[0] = dSpSm/dw, grads[1] = dg2/dw, grads[2] = dSz/dw
+ * of the steady-state observables of twa_run (written to *out), from one
+ * tangent-linear copy ds/dw propagated beside the Heun steps of Eq. (S1) with
+ * the field's own derivative dH/dw = Y/w - Q/(2w) as its source (W is linear
+ * and its PSD square root F square-root homogeneous in w at fixed alpha; Y
+ * the contraction output of a stage, Q its noise part).  About 5/3 of a
+ * forward run in contraction work, no checkpoint store; the cheaper choice
+ * for one parameter (the threshold search in w).  Requires a pump from
+ * twa_build_pump with w > 0; Heun, no lags, precision FP64 / FP32 / BF16 /
+ * FP16.  grads: host, 3 doubles.  Errors as twa_adjoint.
+ */
+TWA_API int twa_tangent_w(const twa_params* p, int64_t n_traj, double dt, int64_t n_steps, uint64_t seed,
+                          twa_observables* out, double* grads);
 
 /* ======================================================================
  * The paper's protocol and threshold quantities.
@@ -399,9 +454,14 @@ typedef struct {
     double w_lo, w_hi;       /* bracket of the pump amplitude w of Eq. (2),
                                 0 < w_lo < w_hi, objective - target changing sign  */
     double tol_w;            /* stop once the Newton correction is below tol_w      */
-    int32_t max_iter;        /* gradient evaluations at most (each one twa_adjoint) */
+    int32_t max_iter;        /* derivative evaluations at most                      */
     int32_t ckpt_every;      /* checkpoint interval of twa_adjoint                  */
+    int32_t derivative;      /* TWA_DERIV_FORWARD (default): twa_tangent_w;         */
+                             /* TWA_DERIV_ADJOINT: the reverse sweep of twa_adjoint */
 } twa_threshold_opts;
+
+#define TWA_DERIV_FORWARD 0
+#define TWA_DERIV_ADJOINT 1
 
 TWA_API void twa_threshold_opts_default(twa_threshold_opts* o);
 
@@ -409,7 +469,8 @@ TWA_API void twa_threshold_opts_default(twa_threshold_opts* o);
  * twa_find_threshold -- the pump amplitude w at which the fixed-noise
  * steady-state objective of twa_run (same seed for every w, so the
  * objective is a smooth function of w) equals o->target, by Newton steps
- * with the pathwise derivative of twa_adjoint, kept inside a bracket that
+ * with the pathwise derivative (twa_tangent_w, or twa_adjoint with
+ * o->derivative = TWA_DERIV_ADJOINT), kept inside a bracket that
  * is bisected whenever a Newton step leaves it.  The pump is factorised once
  * (at w_hi); other amplitudes scale it exactly (W ~ w, F ~ sqrt(w)).  p gives
  * gamma, s0z, burnin, precision, point and tile_config; p->pump is ignored.

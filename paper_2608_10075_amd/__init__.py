@@ -40,7 +40,7 @@ class _Params(C.Structure):
                 ("lag_stride", C.c_int64), ("point", C.c_int32), ("tile_config", C.c_int32),
                 ("stream", C.c_void_p), ("init_state", C.POINTER(C.c_double)), ("timing", C.c_int32),
                 ("use_graph", C.c_int32), ("kappa", C.c_double), ("adjoint_objectives", C.c_int32),
-                ("pump_path", C.c_int32)]
+                ("pump_path", C.c_int32), ("norm_tol", C.c_double)]
 
 
 _OBS_DOUBLES1 = ["T2", "T3", "T4", "Z", "ZZ", "Sz", "SpSm", "g2",
@@ -74,7 +74,9 @@ class _BatchOpts(C.Structure):
     _fields_ = [("n_traj", C.c_int64), ("n_steps", C.c_int64), ("burnin", C.c_int64), ("gamma", C.c_double),
                 ("s0z", C.c_double), ("precision", C.c_int32), ("use_graph", C.c_int32),
                 ("steps_per_graph", C.c_int32), ("tune_cache", C.c_char_p), ("stream", C.c_void_p),
-                ("integrator", C.c_int32)]
+                ("integrator", C.c_int32), ("norm_tol", C.c_double), ("n_lags", C.c_int64),
+                ("lag_stride", C.c_int64), ("kappa", C.c_double), ("tile_config", C.c_int32),
+                ("progress_every", C.c_int64), ("outputs", C.POINTER(_Outs))]
 
 
 class _Protocol(C.Structure):
@@ -84,7 +86,8 @@ class _Protocol(C.Structure):
 
 class _ThresholdOpts(C.Structure):
     _fields_ = [("objective", C.c_int32), ("target", C.c_double), ("w_lo", C.c_double), ("w_hi", C.c_double),
-                ("tol_w", C.c_double), ("max_iter", C.c_int32), ("ckpt_every", C.c_int32)]
+                ("tol_w", C.c_double), ("max_iter", C.c_int32), ("ckpt_every", C.c_int32),
+                ("derivative", C.c_int32)]
 
 
 def load_library(path: str = LIB_PATH) -> C.CDLL:
@@ -112,6 +115,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.twa_run_batch.argtypes = [C.POINTER(_Point), C.c_int, C.POINTER(_BatchOpts), C.POINTER(_Obs)]
     lib.twa_adjoint.argtypes = [C.POINTER(_Params), C.c_int64, C.c_double, C.c_int64, C.c_uint64, C.c_int32,
                                 C.POINTER(_Obs), C.POINTER(C.c_double)]
+    lib.twa_tangent_w.argtypes = [C.POINTER(_Params), C.c_int64, C.c_double, C.c_int64, C.c_uint64,
+                                  C.POINTER(_Obs), C.POINTER(C.c_double)]
     lib.twa_philox.argtypes = [P, C.c_int64, C.c_uint32, C.c_uint32, P, P]
     lib.twa_noise.argtypes = [C.c_uint64, C.c_int64, C.c_int32, C.c_int64, C.c_int64, C.c_int32, P, P, P]
     lib.twa_protocol.argtypes = [P, C.c_double, C.c_double, C.c_int32, C.POINTER(_Protocol)]
@@ -124,7 +129,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
                                C.c_double, C.c_double, C.c_double, C.c_int32, C.POINTER(C.c_double),
                                C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double)]
     for name in ("twa_build_pump", "twa_build_pump_dense", "twa_build_pump_toeplitz", "twa_build_model_dense", "twa_pump_info", "twa_pump_copy_matrix", "twa_run",
-                 "twa_run_batch", "twa_adjoint", "twa_philox", "twa_noise", "twa_protocol", "twa_find_threshold",
+                 "twa_run_batch", "twa_adjoint", "twa_tangent_w", "twa_philox", "twa_noise", "twa_protocol", "twa_find_threshold",
                  "twa_g2_min"):
         getattr(lib, name).restype = C.c_int
     return lib
@@ -250,11 +255,14 @@ def run(pump: Pump, n_traj: int, dt: float, n_steps: int, seed: int = 0, *, gamm
         point: int = 0, tile_config: int = -1, init_state: Optional[np.ndarray] = None, timing: bool = False,
         use_graph: bool = True, kappa: float = 0.25, stream=None, want_traj: bool = False,
         want_final_state: bool = False, want_lags: bool = False, allow_unstable: bool = False,
-        integrator: str = "heun", pump_path: str = "dense") -> RunResult:
+        integrator: str = "heun", pump_path: str = "dense", norm_tol: float = 0.0) -> RunResult:
     """twa_run: n_traj trajectories of Eq. (S1), n_steps steps of size dt of the
     stochastic Heun ("heun") or semi-implicit midpoint ("sib") integrator; the
     pump applied by dense contractions ("dense") or through the circulant
-    embedding of Eq. (2) ("toeplitz")."""
+    embedding of Eq. (2) ("toeplitz").  A run whose spin lengths drift by more
+    than norm_tol (0: the library default 1e-2; < 0: no check) or that produces
+    non-finite values returns TWA_EUNSTABLE: raised as TWAError unless
+    allow_unstable (then ``status`` holds the code and the outputs are kept)."""
     p = _Params()
     _lib.twa_params_default(C.byref(p))
     p.pump = pump.handle
@@ -267,6 +275,7 @@ def run(pump: Pump, n_traj: int, dt: float, n_steps: int, seed: int = 0, *, gamm
     p.timing = 1 if timing else 0
     p.use_graph = 1 if use_graph else 0
     p.kappa = kappa
+    p.norm_tol = norm_tol
     init = None
     if init_state is not None:
         init = np.ascontiguousarray(init_state, dtype=np.float64)
@@ -304,10 +313,16 @@ def run(pump: Pump, n_traj: int, dt: float, n_steps: int, seed: int = 0, *, gamm
 
 def run_batch(points, n_traj: int, n_steps: int, *, burnin: int = -1, gamma: float = 1.0, s0z: float = 1.0,
               precision: str = "fp32", use_graph: bool = True, steps_per_graph: int = 16,
-              tune_cache: Optional[str] = None, stream=None, integrator: str = "heun"):
+              tune_cache: Optional[str] = None, stream=None, integrator: str = "heun", norm_tol: float = 0.0,
+              n_lags: int = 0, lag_stride: int = 0, kappa: float = 0.25, tile_config: int = -1, progress: int = 0,
+              want_traj: bool = False, want_final_state: bool = False, want_lags: bool = False):
     """twa_run_batch: points is a sequence of (N, w, alpha, dt, seed); returns
-    one observables dict per point (Philox point index = position)."""
-    pts = (_Point * len(points))()
+    one observables dict per point (Philox point index = position), or, when
+    per-trajectory arrays are requested (want_*), one RunResult per point.
+    tile_config < 0 lets the library tune one tile configuration per N
+    bucket; progress > 0 prints a line every that many steps."""
+    n = len(points)
+    pts = (_Point * n)()
     for i, (N, w, a, dt, seed) in enumerate(points):
         pts[i].N, pts[i].w, pts[i].alpha, pts[i].dt, pts[i].seed = int(N), float(w), float(a), float(dt), int(seed)
     o = _BatchOpts()
@@ -319,9 +334,42 @@ def run_batch(points, n_traj: int, n_steps: int, *, burnin: int = -1, gamma: flo
     o.tune_cache = tune_cache.encode() if tune_cache else None
     o.stream = _stream_ptr(stream)
     o.integrator = INTEGRATORS[integrator]
-    outs = (_Obs * len(points))()
-    _check(_lib.twa_run_batch(pts, len(points), C.byref(o), outs))
-    return [_obs_dict(x) for x in outs]
+    o.norm_tol = norm_tol
+    o.n_lags, o.lag_stride, o.kappa = n_lags, lag_stride, kappa
+    o.tile_config = tile_config
+    o.progress_every = progress
+    arrays = want_traj or want_final_state or (want_lags and n_lags > 0)
+    results = []
+    if arrays:
+        po = (_Outs * n)()
+        J = min(32, n_traj)
+        keep = []
+        for i, (N, _, _, _, _) in enumerate(points):
+            r = RunResult(obs={})
+            nb = C.c_int32(0)
+            keep.append(nb)
+            po[i].n_blocks = C.pointer(nb)
+            if want_traj:
+                r.traj_moments = np.zeros((n_traj, 5))
+                po[i].traj_moments = r.traj_moments.ctypes.data_as(C.POINTER(C.c_double))
+            if want_final_state:
+                r.final_state = np.zeros((3, n_traj, int(N)))
+                po[i].final_state = r.final_state.ctypes.data_as(C.POINTER(C.c_double))
+            if want_lags and n_lags > 0:
+                r.corr_blocks = np.zeros((n_lags, J, 2))
+                r.chi_blocks = np.zeros((n_lags, J, 4))
+                po[i].corr_blocks = r.corr_blocks.ctypes.data_as(C.POINTER(C.c_double))
+                po[i].chi_blocks = r.chi_blocks.ctypes.data_as(C.POINTER(C.c_double))
+            results.append(r)
+        o.outputs = po
+    outs = (_Obs * n)()
+    _check(_lib.twa_run_batch(pts, n, C.byref(o), outs))
+    if not arrays:
+        return [_obs_dict(x) for x in outs]
+    for i, r in enumerate(results):
+        r.obs = _obs_dict(outs[i])
+        r.n_blocks = keep[i].value
+    return results
 
 
 GRAD_NAMES = ("d_SpSm_dw", "d_SpSm_dalpha", "d_g2_dw", "d_g2_dalpha")
@@ -329,10 +377,12 @@ GRAD_NAMES = ("d_SpSm_dw", "d_SpSm_dalpha", "d_g2_dw", "d_g2_dalpha")
 
 def adjoint(pump: Pump, n_traj: int, dt: float, n_steps: int, seed: int = 0, *, ckpt_every: int = 256,
             gamma: float = 1.0, s0z: float = 1.0, burnin: int = -1, precision: str = "fp32", point: int = 0,
-            tile_config: int = -1, stream=None, objectives=("SpSm", "g2")):
+            tile_config: int = -1, stream=None, objectives=("SpSm", "g2"), norm_tol: float = 0.0,
+            allow_unstable: bool = False):
     """twa_adjoint: observables of the forward run and the pathwise gradients
     d<S+S->/dw, d<S+S->/dalpha, dg2/dw, dg2/dalpha at fixed noise (those of
-    objectives not requested are NaN; each objective costs one reverse copy)."""
+    objectives not requested are NaN; each objective costs one reverse copy).
+    norm_tol and allow_unstable as in ``run``."""
     p = _Params()
     _lib.twa_params_default(C.byref(p))
     p.pump = pump.handle
@@ -343,19 +393,43 @@ def adjoint(pump: Pump, n_traj: int, dt: float, n_steps: int, seed: int = 0, *, 
     p.precision = PRECISIONS[precision]
     p.point, p.tile_config = point, tile_config
     p.stream = _stream_ptr(stream)
+    p.norm_tol = norm_tol
     o = _Obs()
     g = (C.c_double * 4)()
-    _check(_lib.twa_adjoint(C.byref(p), int(n_traj), float(dt), int(n_steps), C.c_uint64(seed & (2 ** 64 - 1)),
-                            int(ckpt_every), C.byref(o), g))
+    rc = _lib.twa_adjoint(C.byref(p), int(n_traj), float(dt), int(n_steps), C.c_uint64(seed & (2 ** 64 - 1)),
+                          int(ckpt_every), C.byref(o), g)
+    if not (rc == TWA_EUNSTABLE and allow_unstable):
+        _check(rc)
     return _obs_dict(o), dict(zip(GRAD_NAMES, list(g)))
 
 
+TANGENT_NAMES = ("d_SpSm_dw", "d_g2_dw", "d_Sz_dw")
+
+
+def tangent_w(pump: Pump, n_traj: int, dt: float, n_steps: int, seed: int = 0, *, gamma: float = 1.0,
+              s0z: float = 1.0, burnin: int = -1, precision: str = "fp32", point: int = 0, tile_config: int = -1,
+              stream=None, norm_tol: float = 0.0, allow_unstable: bool = False):
+    """twa_tangent_w: observables of the forward run and the forward-mode
+    pathwise derivatives d<S+S->/dw, dg2/dw, d<S^z>/dw at fixed noise."""
+    p = _base_params(gamma, s0z, burnin, precision, point, tile_config, stream, norm_tol)
+    p.pump = pump.handle
+    o = _Obs()
+    g = (C.c_double * 3)()
+    rc = _lib.twa_tangent_w(C.byref(p), int(n_traj), float(dt), int(n_steps), C.c_uint64(seed & (2 ** 64 - 1)),
+                            C.byref(o), g)
+    if not (rc == TWA_EUNSTABLE and allow_unstable):
+        _check(rc)
+    return _obs_dict(o), dict(zip(TANGENT_NAMES, list(g)))
+
+
 OBJECTIVES = {"g2": 0, "spsm_n": 1}
+DERIVATIVES = {"forward": 0, "adjoint": 1}
 
 
-def _base_params(gamma, s0z, burnin, precision, point, tile_config, stream):
+def _base_params(gamma, s0z, burnin, precision, point, tile_config, stream, norm_tol=0.0):
     p = _Params()
     _lib.twa_params_default(C.byref(p))
+    p.norm_tol = norm_tol
     p.gamma, p.s0z, p.burnin = gamma, s0z, burnin
     p.precision = PRECISIONS[precision]
     p.point, p.tile_config = point, tile_config
@@ -374,14 +448,18 @@ def protocol(pump: Pump, gamma: float = 1.0, cfl: float = 0.04, finite_size: boo
 def find_threshold(N: int, alpha: float, n_traj: int, dt: float, n_steps: int, seed: int = 0, *,
                    objective: str = "g2", target: float = 1.08, w_lo: float, w_hi: float, tol_w: float = 1e-6,
                    max_iter: int = 30, ckpt_every: int = 256, gamma: float = 1.0, s0z: float = 1.0,
-                   burnin: int = -1, precision: str = "fp32", point: int = 0, tile_config: int = -1, stream=None):
+                   burnin: int = -1, precision: str = "fp32", point: int = 0, tile_config: int = -1, stream=None,
+                   norm_tol: float = 0.0, derivative: str = "forward"):
     """twa_find_threshold: the pump amplitude w where the fixed-noise objective
-    ("g2" or "spsm_n" = <S+S->/N) equals target; returns (w, objective - target,
-    gradient evaluations)."""
-    p = _base_params(gamma, s0z, burnin, precision, point, tile_config, stream)
+    ("g2" or "spsm_n" = <S+S->/N) equals target, by Newton steps with the
+    forward-mode ("forward") or reverse-sweep ("adjoint") pathwise derivative;
+    returns (w, objective - target, derivative evaluations).  norm_tol applies
+    to every run of the search."""
+    p = _base_params(gamma, s0z, burnin, precision, point, tile_config, stream, norm_tol)
     o = _ThresholdOpts()
     _lib.twa_threshold_opts_default(C.byref(o))
     o.objective, o.target, o.w_lo, o.w_hi = OBJECTIVES[objective], target, w_lo, w_hi
+    o.derivative = DERIVATIVES[derivative]
     o.tol_w, o.max_iter, o.ckpt_every = tol_w, max_iter, ckpt_every
     w, f, it = C.c_double(), C.c_double(), C.c_int32()
     _check(_lib.twa_find_threshold(int(N), float(alpha), C.byref(p), int(n_traj), float(dt), int(n_steps),
@@ -392,10 +470,11 @@ def find_threshold(N: int, alpha: float, n_traj: int, dt: float, n_steps: int, s
 
 def g2_min(N: int, alpha: float, n_traj: int, seed: int = 0, *, n_points: int = 10, wt_lo: float = 0.1,
            wt_hi: float = 1.0, cfl: float = 0.04, finite_size: bool = False, gamma: float = 1.0,
-           s0z: float = 1.0, precision: str = "fp32", point: int = 0, tile_config: int = -1, stream=None):
+           s0z: float = 1.0, precision: str = "fp32", point: int = 0, tile_config: int = -1, stream=None,
+           norm_tol: float = 0.0):
     """twa_g2_min: g2 over n_points equally spaced w~ in [wt_lo, wt_hi], each point
     with its own protocol; returns (w~ array, g2 array, w~ of the minimum, g2_min)."""
-    p = _base_params(gamma, s0z, -1, precision, point, tile_config, stream)
+    p = _base_params(gamma, s0z, -1, precision, point, tile_config, stream, norm_tol)
     wt = np.zeros(n_points)
     g2 = np.zeros(n_points)
     wmin, gmin = C.c_double(), C.c_double()
@@ -431,5 +510,5 @@ def noise(seed: int, step: int, n_traj: int, N: int, point: int = 0, fp64: bool 
 
 from .autograd import TWAObservables  # noqa: E402
 
-__all__ = ["Pump", "build_pump", "run", "run_batch", "adjoint", "philox", "noise", "TWAError", "version", "PRECISIONS",
+__all__ = ["Pump", "build_pump", "run", "run_batch", "adjoint", "tangent_w", "philox", "noise", "TWAError", "version", "PRECISIONS",
            "LIB_PATH", "TWAObservables"]

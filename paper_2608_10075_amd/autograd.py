@@ -21,7 +21,8 @@ class TWAObservables(torch.autograd.Function):
             obs, g = adjoint(pump, int(cfg["n_traj"]), float(cfg["dt"]), int(cfg["n_steps"]),
                              int(cfg.get("seed", 0)), ckpt_every=int(cfg.get("ckpt_every", 256)),
                              gamma=float(cfg.get("gamma", 1.0)), s0z=float(cfg.get("s0z", 1.0)),
-                             burnin=int(cfg.get("burnin", -1)), precision=cfg.get("precision", "fp32"))
+                             burnin=int(cfg.get("burnin", -1)), precision=cfg.get("precision", "fp32"),
+                             norm_tol=float(cfg.get("norm_tol", 0.0)))
         finally:
             pump.close()
         ctx.save_for_backward(torch.tensor([[g["d_SpSm_dw"], g["d_SpSm_dalpha"]],

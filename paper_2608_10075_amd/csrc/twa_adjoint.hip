@@ -319,6 +319,10 @@ int adjoint_impl(const twa_params* p, int64_t n_traj, double dt, int64_t n_steps
     double cf[2][5];
     double scale = 0;
     std::vector<double> hmom, hg;
+    std::vector<float> hdiag;
+    const int nblk_fin = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (B * N + 255) / 256));
+    double fwd_norm_dev = 0;
+    bool fwd_nan = false;
     hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
     float fwd_ms = 0.f, bwd_ms = 0.f;
     c.c1 = 0.5 * p->gamma * dt;
@@ -410,12 +414,20 @@ int adjoint_impl(const twa_params* p, int64_t n_traj, double dt, int64_t n_steps
         cur = 1 - cur;
     }
     TWA_HTRY(hipEventRecord(e1, st));
+    // spin-length drift and non-finite values of the forward run's last state
+    TWA_TRY(launch_finish(g, b, cur, nblk_fin, st));
     hmom.resize((size_t)10 * g.Bp);
+    hdiag.resize((size_t)2 * nblk_fin);
     {
         std::vector<S> tmp(hmom.size());
         TWA_HTRY(hipMemcpyAsync(tmp.data(), b.mom, tmp.size() * se, hipMemcpyDeviceToHost, st));
+        TWA_HTRY(hipMemcpyAsync(hdiag.data(), b.diag, hdiag.size() * sizeof(float), hipMemcpyDeviceToHost, st));
         TWA_HTRY(hipStreamSynchronize(st));
         for (size_t i = 0; i < tmp.size(); ++i) hmom[i] = (double)tmp[i];
+        for (int i = 0; i < nblk_fin; ++i) {
+            fwd_norm_dev = std::max(fwd_norm_dev, (double)hdiag[(size_t)i]);
+            if (hdiag[(size_t)nblk_fin + i] != 0.f) fwd_nan = true;
+        }
     }
     {
         const int64_t ns = n_steps - burnin;
@@ -431,6 +443,9 @@ int adjoint_impl(const twa_params* p, int64_t n_traj, double dt, int64_t n_steps
         out->n_samples = ns;
         out->step_criterion = std::max(p->gamma * (double)N, pump->lam_max) * dt;
         out->tile_config = cfg;
+        out->max_norm_dev = fwd_norm_dev;
+        out->nan_flag = fwd_nan ? 1 : 0;
+        if (!std::isfinite(out->SpSm) || !std::isfinite(out->g2)) out->nan_flag = 1;
         if (ns <= 0) {
             set_error("twa_adjoint: empty averaging window");
             rc = TWA_EINVAL;
@@ -548,8 +563,11 @@ int adjoint_impl(const twa_params* p, int64_t n_traj, double dt, int64_t n_steps
     out->kernel_ms = fwd_ms + bwd_ms;
     out->adjoint_fwd_ms = fwd_ms;
     out->adjoint_bwd_ms = bwd_ms;
+    for (int q = 0; q < 4; ++q)
+        if (!std::isnan(grads[q]) && !std::isfinite(grads[q])) out->nan_flag = 1;
+    rc = run_status("twa_adjoint", out->nan_flag != 0, out->max_norm_dev, p->norm_tol);
 cleanup:
-    if (rc != TWA_OK) hipStreamSynchronize(st);
+    if (rc != TWA_OK && rc != TWA_EUNSTABLE) hipStreamSynchronize(st);
     if (e0) hipEventDestroy(e0);
     if (e1) hipEventDestroy(e1);
     if (e2) hipEventDestroy(e2);

@@ -135,6 +135,10 @@ struct GemmCall {
     void *lam = nullptr, *M1 = nullptr, *Rb = nullptr;
     double* gacc = nullptr;
     double inv_w = 0;
+    // response / parameter tangent copies (kind 1): their state, increment,
+    // field and operands; with Qin set, kind 1 adds the w-source Y/w - Q/(2w)
+    const void* t_cur = nullptr;
+    void *t_next = nullptr, *t_dlt = nullptr, *tY = nullptr, *tDop = nullptr;
     double srccoef[2][5] = {{0}};
     double src_scale = 0;
     int src_on = 0;
@@ -143,16 +147,35 @@ int launch_gemm_call(const Geometry& g, const GemmCall& c, hipStream_t st);
 
 // Grouped persistent contraction launches over many ensembles that share a
 // precision and tile configuration (one launch per stage covers all of them).
+// Variants of a stage: the plain primal step, the primal step inside a
+// two-time window (predictor increment kept, corrector field stored for the
+// response copies) and the two response copies themselves.
+enum { GV_PRIMAL = 0, GV_PRIMAL_TAN = 1, GV_TANGENT = 2, GV_COUNT = 3 };
 struct GroupedPlan {
-    void* d_args[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};   // [stage-1][cur] per-ensemble arguments
-    int4* d_tiles[2] = {nullptr, nullptr};
+    void* d_args[GV_COUNT][2][2] = {};   // [variant][stage-1][cur] per-ensemble arguments
+    int4* d_tiles[2] = {nullptr, nullptr};   // [0] (point, M tile, column tile, 0); [1] also copy 1
     int ntiles[2] = {0, 0};
-    int grid = 0, cfg = 0, precision = 0, integrator = TWA_INT_HEUN;
+    int grid[2] = {0, 0};
+    int cfg = 0, precision = 0, integrator = TWA_INT_HEUN;
+    bool tangents = false;
     int64_t* step = nullptr;
 };
 int grouped_prepare(const std::vector<Geometry>& gs, const std::vector<EnsembleBuffers>& bs,
-                    const std::vector<StepConsts>& cs, int64_t* step, GroupedPlan& pl);
-int grouped_launch(const GroupedPlan& pl, int stage, int cur, hipStream_t st);
+                    const std::vector<StepConsts>& cs, int64_t* step, bool tangents, GroupedPlan& pl);
+// per-precision launchers, instantiated one precision per translation unit
+// (twa_step_<precision>.hip); launch_gemm, launch_gemm_call, grouped_prepare
+// and grouped_launch dispatch to them
+template <int PREC>
+int launch_gemm_p(const Geometry& g, const EnsembleBuffers& b, const StepConsts& c, int stage, bool tangent, int cur,
+                  bool store_y2, bool keep_dlt, hipStream_t st);
+template <int PREC>
+int launch_call_p(const Geometry& g, const GemmCall& c, hipStream_t st);
+template <int PREC>
+int grouped_prepare_p(const std::vector<Geometry>& gs, const std::vector<EnsembleBuffers>& bs,
+                      const std::vector<StepConsts>& cs, int64_t* step, bool tangents, GroupedPlan& pl);
+template <int PREC>
+int grouped_launch_p(const GroupedPlan& pl, int stage, int cur, int variant, hipStream_t st);
+int grouped_launch(const GroupedPlan& pl, int stage, int cur, int variant, hipStream_t st);
 void grouped_free(GroupedPlan& pl);
 
 // kernel launchers (twa_step.hip, twa_aux.hip)

@@ -105,6 +105,7 @@ TWA_API void twa_threshold_opts_default(twa_threshold_opts* o) {
     o->tol_w = 1e-6;
     o->max_iter = 30;
     o->ckpt_every = 256;
+    o->derivative = TWA_DERIV_FORWARD;
 }
 
 TWA_API int twa_find_threshold(int64_t N, double alpha, const twa_params* p, int64_t n_traj, double dt,
@@ -113,6 +114,7 @@ TWA_API int twa_find_threshold(int64_t N, double alpha, const twa_params* p, int
     using namespace twa;
     if (!p || !o || N < 1 || !(alpha >= 0) || !std::isfinite(alpha) || !(o->w_lo > 0) ||
         !(o->w_hi > o->w_lo) || !std::isfinite(o->w_hi) || !(o->tol_w > 0) || o->max_iter < 1 ||
+        (o->derivative != TWA_DERIV_FORWARD && o->derivative != TWA_DERIV_ADJOINT) ||
         (o->objective != TWA_OBJ_G2 && o->objective != TWA_OBJ_SPSM_N) || !std::isfinite(o->target)) {
         set_error("twa_find_threshold: need params, options with 0 < w_lo < w_hi, tol_w > 0, max_iter >= 1 and a "
                   "known objective");
@@ -133,10 +135,14 @@ TWA_API int twa_find_threshold(int64_t N, double alpha, const twa_params* p, int
         q.adjoint_objectives = o->objective == TWA_OBJ_G2 ? 2 : 1;
         twa_observables ob;
         std::memset(&ob, 0, sizeof(ob));
-        if (grad) {
+        if (grad && o->derivative == TWA_DERIV_ADJOINT) {
             double g[4] = {0, 0, 0, 0};
             e = twa_adjoint(&q, n_traj, dt, n_steps, seed, ck, &ob, g);
             if (!e) *grad = o->objective == TWA_OBJ_G2 ? g[2] : g[0] / (double)N;
+        } else if (grad) {
+            double g[3] = {0, 0, 0};
+            e = twa_tangent_w(&q, n_traj, dt, n_steps, seed, &ob, g);
+            if (!e) *grad = o->objective == TWA_OBJ_G2 ? g[1] : g[0] / (double)N;
         } else {
             e = twa_run(&q, n_traj, dt, n_steps, seed, &ob, nullptr);
         }

@@ -50,12 +50,22 @@ struct StepTimer {
     }
 };
 
+// spin-length check of a run: the threshold on max_norm_dev (0: the default
+// 1e-2; < 0: no check), and the status and message of a finished run
+inline double effective_norm_tol(double t) { return t == 0 ? 1e-2 : t; }
+int run_status(const char* who, bool nan, double max_norm_dev, double norm_tol);
+
 void free_buffers(EnsembleBuffers& b);
 int alloc_buffers(const Geometry& g, bool tangents, int64_t L, int J, EnsembleBuffers& b);
 Geometry make_geometry(int precision, int cfg, int64_t N, int64_t B);
 void finalize_moments(const std::vector<double>& traj, int64_t B, twa_observables* o);
 void finalize_decay(const std::vector<double>& traj, int64_t B, twa_observables* o);
 double linewidth_of(const std::vector<std::complex<double>>& corr, double tau);
+// two-time finalisation: lag sums hlag [L][J][6] (block sums of the symmetric
+// part and of the four response curves) -> out->linewidth, linewidth_sym and
+// the optional corr_blocks / chi_blocks of outs
+void finalize_lags(const std::vector<double>& hlag, int64_t L, int J, int64_t B, int64_t stride, double dt,
+                   double kappa, twa_observables* out, const twa_outputs* outs);
 
 // per-launch timers for the two contraction stages (primal)
 struct GemmTimers {
@@ -66,5 +76,7 @@ int launch_step_kernels(const Geometry& g, EnsembleBuffers& b, const StepConsts&
                         GemmTimers* tm, hipStream_t st);
 int run_single(const twa_params* p, int64_t n_traj, double dt, int64_t n_steps, uint64_t seed,
                twa_observables* out, const twa_outputs* outs);
+int run_tangent_w(const twa_params* p, int64_t n_traj, double dt, int64_t n_steps, uint64_t seed,
+                  twa_observables* out, double* grads);
 
 }  // namespace twa

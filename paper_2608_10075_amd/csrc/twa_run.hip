@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <cstdio>
 #include <cstring>
 #include <vector>
 
@@ -227,6 +228,51 @@ double linewidth_of(const std::vector<std::complex<double>>& corr, double tau) {
     return right - left;
 }
 
+int run_status(const char* who, bool nan, double max_norm_dev, double norm_tol) {
+    const double tol = effective_norm_tol(norm_tol);
+    if (nan) {
+        set_error(std::string(who) + ": non-finite values in the state or accumulators");
+        return TWA_EUNSTABLE;
+    }
+    if (tol > 0 && !(max_norm_dev <= tol)) {
+        char buf[192];
+        std::snprintf(buf, sizeof(buf),
+                      "%s: a spin length drifted by %.3g (max_norm_dev) > norm_tol %.3g; Eq. (S1) conserves "
+                      "|s_i|^2 -- reduce dt or use the semi-implicit integrator",
+                      who, max_norm_dev, tol);
+        set_error(buf);
+        return TWA_EUNSTABLE;
+    }
+    return TWA_OK;
+}
+
+void finalize_lags(const std::vector<double>& hlag, int64_t L, int J, int64_t B, int64_t stride, double dt,
+                   double kappa, twa_observables* out, const twa_outputs* outs) {
+    std::vector<std::complex<double>> corr((size_t)L), csym((size_t)L);
+    for (int64_t l = 0; l < L; ++l) {
+        double s[6] = {0, 0, 0, 0, 0, 0};
+        for (int j = 0; j < J; ++j)
+            for (int q = 0; q < 6; ++q) s[q] += hlag[((size_t)l * J + j) * 6 + q];
+        for (int q = 0; q < 6; ++q) s[q] /= (double)B;
+        const std::complex<double> cs(s[0], s[1]);
+        // kappa * i * (xx + yy + i yx - i xy)
+        const std::complex<double> resp(s[2] + s[5], s[3] - s[4]);
+        csym[(size_t)l] = cs;
+        corr[(size_t)l] = cs + std::complex<double>(0.0, kappa) * resp;
+    }
+    const double tau = (double)stride * dt;
+    out->linewidth = linewidth_of(corr, tau);
+    out->linewidth_sym = linewidth_of(csym, tau);
+    if (outs && outs->corr_blocks)
+        for (size_t q = 0; q < (size_t)L * J; ++q) {
+            outs->corr_blocks[2 * q] = hlag[6 * q];
+            outs->corr_blocks[2 * q + 1] = hlag[6 * q + 1];
+        }
+    if (outs && outs->chi_blocks)
+        for (size_t q = 0; q < (size_t)L * J; ++q)
+            for (int r = 0; r < 4; ++r) outs->chi_blocks[4 * q + r] = hlag[6 * q + 2 + r];
+}
+
 // ---------------------------------------------------------------------------
 void free_buffers(EnsembleBuffers& b) {
     void* ptrs[] = {b.A,      b.Xop,    b.Dop,  b.s[0], b.s[1],    b.dlt,     b.Y,      b.part[0],
@@ -346,6 +392,9 @@ TWA_API void twa_params_default(twa_params* p) {
     p->timing = 0;
     p->use_graph = 1;
     p->kappa = 0.25;
+    p->adjoint_objectives = 0;
+    p->pump_path = TWA_PUMP_DENSE;
+    p->norm_tol = 1e-2;
 }
 
 TWA_API int twa_philox(const uint32_t* ctr, int64_t n, uint32_t key0, uint32_t key1, uint32_t* out, void* stream) {

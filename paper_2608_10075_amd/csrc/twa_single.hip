@@ -358,35 +358,10 @@ int run_single(const twa_params* p, int64_t n_traj, double dt, int64_t n_steps, 
         }
         out->linewidth = NAN;
         out->linewidth_sym = NAN;
-        if (L > 0) {
-            std::vector<std::complex<double>> corr((size_t)L), csym((size_t)L);
-            for (int64_t l = 0; l < L; ++l) {
-                double s[6] = {0, 0, 0, 0, 0, 0};
-                for (int j = 0; j < J; ++j)
-                    for (int q = 0; q < 6; ++q) s[q] += hlag[((size_t)l * J + j) * 6 + q];
-                for (int q = 0; q < 6; ++q) s[q] /= (double)B;
-                const std::complex<double> cs(s[0], s[1]);
-                // kappa * i * (xx + yy + i yx - i xy)
-                const std::complex<double> resp(s[2] + s[5], s[3] - s[4]);
-                csym[(size_t)l] = cs;
-                corr[(size_t)l] = cs + std::complex<double>(0.0, p->kappa) * resp;
-            }
-            const double tau = (double)stride * dt;
-            out->linewidth = linewidth_of(corr, tau);
-            out->linewidth_sym = linewidth_of(csym, tau);
-            if (outs && outs->corr_blocks)
-                for (size_t q = 0; q < (size_t)L * J; ++q) {
-                    outs->corr_blocks[2 * q] = hlag[6 * q];
-                    outs->corr_blocks[2 * q + 1] = hlag[6 * q + 1];
-                }
-            if (outs && outs->chi_blocks)
-                for (size_t q = 0; q < (size_t)L * J; ++q)
-                    for (int r = 0; r < 4; ++r) outs->chi_blocks[4 * q + r] = hlag[6 * q + 2 + r];
-        }
+        if (L > 0) finalize_lags(hlag, L, J, B, stride, dt, p->kappa, out, outs);
         if (outs && outs->traj_moments) std::memcpy(outs->traj_moments, traj.data(), traj.size() * sizeof(double));
         if (outs && outs->n_blocks) *outs->n_blocks = J;
-        rc = nan ? TWA_EUNSTABLE : TWA_OK;
-        if (nan) set_error("twa_run: non-finite values in the state or accumulators");
+        rc = run_status("twa_run", nan, mx, p->norm_tol);
     }
 cleanup:
     if (rc != TWA_OK && rc != TWA_EUNSTABLE) hipStreamSynchronize(st);

@@ -6,7 +6,8 @@ trajectories of the ensemble (``RunConfig.traj``).
 
 Workloads (all synthetic, the method's own Philox stream):
   * N = 1e4, alpha = 1, w = ln N, 1024 trajectories, dt = 1e-4 (the headline
-    workload; BF16 and FP32 contractions), sampled trajectories over 20 steps;
+    workload; BF16, FP32 and FP64 contractions, Heun and semi-implicit),
+    sampled trajectories over 20 and 10^3 steps;
   * N = 16, alpha = 1, w = 4, 512 trajectories, dt = 1e-3, 2e4 steps, atoms
     initially down, FP64: every trajectory and the ensemble observables;
   * N = 1000, alpha = 1, w = 1, 4096 trajectories, dt = 1e-4, 1e3 steps,
@@ -39,33 +40,63 @@ def _max_rel_traj(g, o):
     return float(np.max(np.linalg.norm(g - o, axis=1) / np.linalg.norm(o, axis=1)))
 
 
+HEADLINE = dict(N=10000, alpha=1.0, B=1024, dt=1e-4, w=math.log(10000))
+HEADLINE_IDX = np.array([0, 1, 513, 1023])
+
+
 @pytest.fixture(scope="module")
 def headline(twa):
-    N, alpha, B, dt, T = 10000, 1.0, 1024, 1e-4, 20
-    w = math.log(N)
-    idx = np.array([0, 1, 513, 1023])
-    pump = twa.build_pump(N, w, alpha)
-    ref = otwa.run(otwa.RunConfig(n_spin=N, w=w, alpha=alpha, n_traj=len(idx), dt=dt, n_steps=T, seed=0,
-                                  traj=idx), opump.build_pump(N, w, alpha))
-    return dict(N=N, alpha=alpha, B=B, dt=dt, T=T, w=w, idx=idx, pump=pump, ref=ref)
+    """GPU pump of the headline workload and the oracle's sampled trajectories
+    (computed on first use, per integrator and step count)."""
+    h = HEADLINE
+    gpump = twa.build_pump(h["N"], h["w"], h["alpha"])
+    opump_ = opump.build_pump(h["N"], h["w"], h["alpha"])
+    cache = {}
+
+    def ref(integ, T):
+        if (integ, T) not in cache:
+            cfg = otwa.RunConfig(n_spin=h["N"], w=h["w"], alpha=h["alpha"], n_traj=len(HEADLINE_IDX), dt=h["dt"],
+                                 n_steps=T, seed=0, traj=HEADLINE_IDX, integrator=integ)
+            cache[(integ, T)] = otwa.run(cfg, opump_)
+        return cache[(integ, T)]
+    return dict(pump=gpump, ref=ref)
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16"])
-def test_headline_workload_sampled_trajectories(twa, headline, prec):
-    h = headline
-    r = twa.run(h["pump"], h["B"], h["dt"], h["T"], seed=0, precision=prec, want_final_state=True,
-                want_traj=True)
-    g = r.final_state[:, h["idx"], :]
-    rel = _max_rel_traj(g, h["ref"].final_state)
-    mom = r.traj_moments[h["idx"]]
-    mrel = float(np.max(np.abs(mom - h["ref"].traj_moments) / np.abs(h["ref"].traj_moments).max(axis=0)))
-    print("N=1e4 %s tile %d: state rel %.3e moments rel %.3e" % (prec, r.obs["tile_config"], rel, mrel))
-    # FP32: rounding of the FP32 state and operands only (1e-5 as at the smaller
-    # sizes).  BF16: each step's contracted field increment (|dt/2 W s| +
-    # |sqrt(dt) F zeta| ~ 0.04 of a spin at this workload) carries at most 2 u
-    # relative error (u = 2^-9 for both operands), accumulated over 20 steps
-    # without cancellation: 20 * 0.04 * 2^-8 ~ 3e-3.
+def _compare(twa, headline, integ, prec, T):
+    h = HEADLINE
+    r = twa.run(headline["pump"], h["B"], h["dt"], T, seed=0, precision=prec, integrator=integ,
+                want_final_state=True, want_traj=True, norm_tol=-1)
+    ref = headline["ref"](integ, T)
+    rel = _max_rel_traj(r.final_state[:, HEADLINE_IDX, :], ref.final_state)
+    mom = r.traj_moments[HEADLINE_IDX]
+    mrel = float(np.max(np.abs(mom - ref.traj_moments) / np.abs(ref.traj_moments).max(axis=0)))
+    print("N=1e4 %s %s %d steps tile %d: state rel %.3e moments rel %.3e norm dev %.3g" % (
+        integ, prec, T, r.obs["tile_config"], rel, mrel, r.obs["max_norm_dev"]))
+    return rel, mrel
+
+
+@pytest.mark.parametrize("integ,prec", [("heun", "fp32"), ("heun", "bf16"), ("sib", "bf16")])
+def test_headline_workload_sampled_trajectories(twa, headline, integ, prec):
+    """20 steps of the headline workload, including the BF16 semi-implicit run
+    the bench times.  FP32: rounding of the FP32 state and operands only
+    (1e-5).  BF16: each step's contracted field increment (|dt/2 W s| +
+    |sqrt(dt) F zeta| ~ 0.04 of a spin at this workload) carries at most 2 u
+    relative error (u = 2^-9 for both operands), accumulated over 20 steps
+    without cancellation: 20 * 0.04 * 2^-8 ~ 3e-3."""
+    rel, mrel = _compare(twa, headline, integ, prec, 20)
     tol = {"fp32": 1e-5, "bf16": 5e-3}[prec]
+    assert rel < tol, rel
+    assert mrel < tol, mrel
+
+
+@pytest.mark.parametrize("integ,prec", [("sib", "fp32"), ("sib", "fp64"), ("heun", "fp32"), ("heun", "fp64")])
+def test_headline_workload_1e3_steps(twa, headline, integ, prec):
+    """10^3 steps of the headline workload (step criterion max(Gamma N,
+    lam_max) dt = 1.0) on sampled trajectories, in the launch configuration
+    of the bench (1024 trajectories, default tiles: 320x256 in FP32, 128x128
+    in FP64), FP32 at 1e-5 and FP64 at 1e-10 per trajectory."""
+    rel, mrel = _compare(twa, headline, integ, prec, 1000)
+    tol = {"fp32": 1e-5, "fp64": 1e-10}[prec]
     assert rel < tol, rel
     assert mrel < tol, mrel
 
@@ -73,7 +104,7 @@ def test_headline_workload_sampled_trajectories(twa, headline, prec):
 def test_fp64_workload_n16_all_trajectories_and_ensemble(twa):
     N, alpha, w, B, dt, T = 16, 1.0, 4.0, 512, 1e-3, 20000
     pump = twa.build_pump(N, w, alpha)
-    r = twa.run(pump, B, dt, T, seed=0, precision="fp64", s0z=-1.0, want_final_state=True, want_traj=True)
+    r = twa.run(pump, B, dt, T, seed=0, precision="fp64", s0z=-1.0, want_final_state=True, want_traj=True, norm_tol=-1)
     ref = otwa.run(otwa.RunConfig(n_spin=N, w=w, alpha=alpha, n_traj=B, dt=dt, n_steps=T, seed=0, s0z=-1.0),
                    opump.build_pump(N, w, alpha))
     rel = _max_rel_traj(r.final_state, ref.final_state)
@@ -90,7 +121,7 @@ def test_fp32_workload_n1000_sampled_trajectories(twa):
     N, alpha, w, B, dt, T = 1000, 1.0, 1.0, 4096, 1e-4, 1000
     idx = np.array([0, 1, 2047, 4095])
     pump = twa.build_pump(N, w, alpha)
-    r = twa.run(pump, B, dt, T, seed=0, precision="fp32", want_final_state=True)
+    r = twa.run(pump, B, dt, T, seed=0, precision="fp32", want_final_state=True, norm_tol=-1)
     ref = otwa.run(otwa.RunConfig(n_spin=N, w=w, alpha=alpha, n_traj=len(idx), dt=dt, n_steps=T, seed=0,
                                   traj=idx), opump.build_pump(N, w, alpha))
     rel = _max_rel_traj(r.final_state[:, idx, :], ref.final_state)

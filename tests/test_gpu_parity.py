@@ -7,6 +7,10 @@ layout on both sides, implemented independently), or states from
   * FP64 path: 1e-10 relative-to-scale (rounding order only differs);
   * FP32 path: 1e-5 relative per trajectory over 1e3 steps;
   * BF16/FP16: stated error against FP64 (no parity claim).
+Parity at fixed noise holds whatever the spin-length drift of the integrator,
+so these runs switch the drift check off (norm_tol=-1); the check itself
+(TWA_EUNSTABLE beyond norm_tol, default 1e-2) is tested in
+test_norm_drift_flag.
 """
 import numpy as np
 import pytest
@@ -76,7 +80,7 @@ def test_fp64_trajectories_match_oracle(twa, N, B, cfg):
     w, alpha, dt, T, seed = 3.0, 1.0, 1e-3, 120, 11
     p = twa.build_pump(N, w, alpha)
     r = twa.run(p, B, dt, T, seed=seed, precision="fp64", tile_config=cfg, s0z=-1.0,
-                want_traj=True, want_final_state=True)
+                want_traj=True, want_final_state=True, norm_tol=-1)
     ref = _oracle(N, w, alpha, B, dt, T, seed, s0z=-1.0)
     for c in range(3):
         assert np.max(np.abs(r.final_state[c] - ref.final_state[c])) < 1e-11
@@ -93,7 +97,7 @@ def test_fp32_trajectories_1e3_steps(twa, N, B, cfg):
     T = 1000 if N < 600 else 300     # keeps the oracle within seconds at the larger tiles
     dt = 0.02 / N
     p = twa.build_pump(N, w, alpha)
-    r = twa.run(p, B, dt, T, seed=seed, precision="fp32", tile_config=cfg, want_final_state=True)
+    r = twa.run(p, B, dt, T, seed=seed, precision="fp32", tile_config=cfg, want_final_state=True, norm_tol=-1)
     ref = _oracle(N, w, alpha, B, dt, T, seed)
     g = r.final_state.transpose(1, 0, 2).reshape(B, -1)
     o = np.stack(ref.final_state).transpose(1, 0, 2).reshape(B, -1)
@@ -107,7 +111,7 @@ def test_custom_initial_state_single_step(twa):
     w, alpha, dt = 2.5, 0.7, 2e-3
     p = twa.build_pump(N, w, alpha)
     for prec, tol in (("fp64", 1e-13), ("fp32", 2e-6)):
-        r = twa.run(p, B, dt, 1, seed=4, precision=prec, init_state=init, want_final_state=True)
+        r = twa.run(p, B, dt, 1, seed=4, precision=prec, init_state=init, want_final_state=True, norm_tol=-1)
         ref = _oracle(N, w, alpha, B, dt, 1, 4, init_state=tuple(init))
         for c in range(3):
             assert np.max(np.abs(r.final_state[c] - ref.final_state[c])) < tol
@@ -117,7 +121,7 @@ def test_two_time_fp64_matches_oracle(twa):
     N, B, w, alpha, dt, T, seed = 10, 40, 2.0, 1.0, 1e-3, 400, 2
     p = twa.build_pump(N, w, alpha)
     r = twa.run(p, B, dt, T, seed=seed, precision="fp64", burnin=200, n_lags=20, lag_stride=10,
-                want_lags=True, want_traj=True)
+                want_lags=True, want_traj=True, norm_tol=-1)
     ref = _oracle(N, w, alpha, B, dt, T, seed, burnin=200, n_lags=20, lag_stride=10)
     corr = r.corr_blocks[..., 0] + 1j * r.corr_blocks[..., 1]          # (L, J)
     assert np.max(np.abs(corr.T - ref.corr_blocks)) < 1e-9 * np.abs(ref.corr_blocks).max()
@@ -134,7 +138,7 @@ def test_two_time_fp64_matches_oracle(twa):
 def test_two_time_fp32(twa):
     N, B, w, alpha, dt, T, seed = 40, 48, 2.0, 1.0, 5e-4, 600, 9
     p = twa.build_pump(N, w, alpha)
-    r = twa.run(p, B, dt, T, seed=seed, precision="fp32", burnin=300, n_lags=30, lag_stride=10, want_lags=True)
+    r = twa.run(p, B, dt, T, seed=seed, precision="fp32", burnin=300, n_lags=30, lag_stride=10, want_lags=True, norm_tol=-1)
     ref = _oracle(N, w, alpha, B, dt, T, seed, burnin=300, n_lags=30, lag_stride=10)
     corr = (r.corr_blocks[..., 0] + 1j * r.corr_blocks[..., 1]).T
     assert np.max(np.abs(corr - ref.corr_blocks)) < 1e-5 * np.abs(ref.corr_blocks).max()
@@ -149,7 +153,7 @@ def test_reduced_precision_error_is_bounded(twa, prec, tol, cfg):
     N, B, w, alpha, T = (128, 64, 2.0, 1.0, 200) if cfg < 7 else (400, 150, 2.0, 1.0, 100)
     dt = 0.02 / N
     p = twa.build_pump(N, w, alpha)
-    r = twa.run(p, B, dt, T, seed=1, precision=prec, tile_config=cfg, want_final_state=True)
+    r = twa.run(p, B, dt, T, seed=1, precision=prec, tile_config=cfg, want_final_state=True, norm_tol=-1)
     ref = _oracle(N, w, alpha, B, dt, T, 1)
     err = max(np.max(np.abs(r.final_state[c] - ref.final_state[c])) for c in range(3))
     assert err < tol, err
@@ -158,7 +162,7 @@ def test_reduced_precision_error_is_bounded(twa, prec, tol, cfg):
 def test_observables_match_oracle_finaliser(twa):
     N, B, w, alpha, dt, T = 16, 64, 4.0, 1.0, 1e-3, 600
     p = twa.build_pump(N, w, alpha)
-    r = twa.run(p, B, dt, T, seed=0, precision="fp64", s0z=-1.0)
+    r = twa.run(p, B, dt, T, seed=0, precision="fp64", s0z=-1.0, norm_tol=-1)
     ref = _oracle(N, w, alpha, B, dt, T, 0, s0z=-1.0)
     o = oobs.finalize(ref.traj_moments)
     for k in ("Sz", "SpSm", "g2", "T2", "T3", "T4", "Z", "ZZ", "g2_se", "SpSm_se"):
@@ -169,27 +173,66 @@ def test_determinism_and_graph_replay(twa):
     N, B, T = 70, 36, 100
     p = twa.build_pump(N, 1.5, 0.8)
     a = twa.run(p, B, 1e-3, T, seed=8, use_graph=True, want_final_state=True, n_lags=5, lag_stride=8,
-                burnin=40, want_lags=True)
+                burnin=40, want_lags=True, norm_tol=-1)
     b = twa.run(p, B, 1e-3, T, seed=8, use_graph=False, want_final_state=True, n_lags=5, lag_stride=8,
-                burnin=40, want_lags=True)
+                burnin=40, want_lags=True, norm_tol=-1)
     c = twa.run(p, B, 1e-3, T, seed=8, use_graph=True, want_final_state=True, n_lags=5, lag_stride=8,
-                burnin=40, want_lags=True)
+                burnin=40, want_lags=True, norm_tol=-1)
     assert np.array_equal(a.final_state, b.final_state) and np.array_equal(a.final_state, c.final_state)
     assert np.array_equal(a.corr_blocks, b.corr_blocks) and np.array_equal(a.chi_blocks, c.chi_blocks)
 
 
 def test_edge_cases(twa):
     p = twa.build_pump(1, 2.0, 1.0)
-    r = twa.run(p, 1, 1e-3, 50, seed=1, precision="fp64", want_final_state=True)
+    r = twa.run(p, 1, 1e-3, 50, seed=1, precision="fp64", want_final_state=True, norm_tol=-1)
     ref = _oracle(1, 2.0, 1.0, 1, 1e-3, 50, 1)
     assert np.max(np.abs(r.final_state - np.stack(ref.final_state))) < 1e-12
     p = twa.build_pump(5, 1.0, 1.0)
-    r = twa.run(p, 3, 1e-3, 0, seed=1, want_final_state=True, allow_unstable=True)
+    r = twa.run(p, 3, 1e-3, 0, seed=1, want_final_state=True, allow_unstable=True, norm_tol=-1)
     x, y, z = otwa.initial_state(1, 3, 5)
     assert np.array_equal(r.final_state, np.stack([x, y, z]))
     with pytest.raises(twa.TWAError):
-        twa.run(p, 3, 1e-3, 10, burnin=11)
+        twa.run(p, 3, 1e-3, 10, burnin=11, norm_tol=-1)
     with pytest.raises(twa.TWAError):
-        twa.run(p, 3, 1e-3, 10, burnin=5, n_lags=4, lag_stride=2)
+        twa.run(p, 3, 1e-3, 10, burnin=5, n_lags=4, lag_stride=2, norm_tol=-1)
     with pytest.raises(twa.TWAError):
-        twa.run(p, 0, 1e-3, 10)
+        twa.run(p, 0, 1e-3, 10, norm_tol=-1)
+
+
+def test_norm_drift_flag(twa):
+    """Eq. (S1) conserves every |s_i|^2: a run whose spin lengths drift past
+    norm_tol (default 1e-2) returns TWA_EUNSTABLE with its outputs written;
+    the semi-implicit scheme keeps the lengths and passes the default check.
+    Workload: the FP64 configuration (N = 16, alpha = 1, w = 4, atoms down,
+    dt = 1e-3) over 4000 steps, where Heun drifts by a few percent; the fused
+    small-N kernel, the multi-kernel path (tile 0), the adjoint and the batch."""
+    N, B, w, alpha, dt, T = 16, 32, 4.0, 1.0, 1e-3, 4000
+    p = twa.build_pump(N, w, alpha)
+    for cfg in (-1, 0):
+        with pytest.raises(twa.TWAError) as e:
+            twa.run(p, B, dt, T, seed=1, precision="fp64", s0z=-1.0, tile_config=cfg)
+        assert e.value.code == twa.TWA_EUNSTABLE and "drifted" in str(e.value)
+        r = twa.run(p, B, dt, T, seed=1, precision="fp64", s0z=-1.0, tile_config=cfg, allow_unstable=True,
+                    want_final_state=True)
+        off = twa.run(p, B, dt, T, seed=1, precision="fp64", s0z=-1.0, tile_config=cfg, norm_tol=-1,
+                      want_final_state=True)
+        assert r.status == twa.TWA_EUNSTABLE and off.status == twa.TWA_OK
+        dev = r.obs["max_norm_dev"]
+        assert dev > 1e-2 and np.isfinite(r.obs["g2"]) and r.obs["nan_flag"] == 0
+        assert np.array_equal(r.final_state, off.final_state) and r.obs["g2"] == off.obs["g2"]
+        # the drift equals the largest | |s|^2 - |s0|^2 | of the returned state (|s0|^2 = 3),
+        # reduced on the device in binary32
+        norms = (r.final_state ** 2).sum(axis=0)
+        assert abs(dev - np.max(np.abs(norms - 3.0))) < 1e-6 * dev
+        assert twa.run(p, B, dt, T, seed=1, precision="fp64", s0z=-1.0, tile_config=cfg,
+                       norm_tol=2 * dev).status == twa.TWA_OK
+        s = twa.run(p, B, dt, T, seed=1, precision="fp64", s0z=-1.0, tile_config=cfg, integrator="sib")
+        assert s.status == twa.TWA_OK and s.obs["max_norm_dev"] < 1e-10
+    with pytest.raises(twa.TWAError) as e:
+        twa.adjoint(p, B, dt, T, seed=1, precision="fp64", s0z=-1.0)
+    assert e.value.code == twa.TWA_EUNSTABLE
+    obs, g = twa.adjoint(p, B, dt, T, seed=1, precision="fp64", s0z=-1.0, allow_unstable=True)
+    assert obs["max_norm_dev"] > 1e-2 and all(np.isfinite(v) for v in g.values())
+    with pytest.raises(twa.TWAError) as e:
+        twa.run_batch([(N, w, alpha, dt, 0), (40, w, alpha, dt, 1)], B, T, s0z=-1.0)
+    assert e.value.code == twa.TWA_EUNSTABLE

@@ -1,7 +1,8 @@
 """The paper's protocol and threshold quantities through the C ABI against the
 oracle: the per-point protocol (step criterion, preparation time, window),
-the fixed-noise threshold search (Newton steps with the adjoint gradient vs
-the oracle's bisection on its own runs), and the g2_min scan."""
+the fixed-noise threshold search (Newton steps with the forward-mode or
+reverse-sweep pathwise derivative vs the oracle's bisection on its own runs),
+and the g2_min scan."""
 import numpy as np
 import pytest
 
@@ -33,14 +34,16 @@ def test_protocol_matches_oracle(twa, N, w, alpha, fs):
 N_T, ALPHA_T, B_T, DT_T, T_T, BURN_T, SEED_T = 10, 1.0, 256, 2e-3, 600, 300, 3
 
 
-@pytest.mark.parametrize("objective,target", [("spsm_n", 1.0), ("g2", 1.7)])
-def test_threshold_matches_oracle_bisection(twa, objective, target):
+@pytest.mark.parametrize("objective,target,deriv", [("spsm_n", 1.0, "forward"), ("g2", 1.7, "forward"),
+                                                    ("spsm_n", 1.0, "adjoint"), ("g2", 1.7, "adjoint")])
+def test_threshold_matches_oracle_bisection(twa, objective, target, deriv):
     w, f, it = twa.find_threshold(N_T, ALPHA_T, B_T, DT_T, T_T, SEED_T, objective=objective, target=target,
-                                  w_lo=1.0, w_hi=2.0, tol_w=1e-10, precision="fp64", burnin=BURN_T)
+                                  w_lo=1.0, w_hi=2.0, tol_w=1e-10, precision="fp64", burnin=BURN_T, norm_tol=-1,
+                                  derivative=deriv)
     ref = oprot.bisect(lambda x: oprot.objective(N_T, x, ALPHA_T, B_T, DT_T, T_T, BURN_T, SEED_T, objective),
                        1.0, 2.0, target, tol=1e-10)
-    print("threshold %s = %g: GPU w %.12f (%d gradient evaluations, residual %.2e), oracle %.12f"
-          % (objective, target, w, it, f, ref))
+    print("threshold %s = %g (%s): GPU w %.12f (%d derivative evaluations, residual %.2e), oracle %.12f"
+          % (objective, target, deriv, w, it, f, ref))
     assert abs(w - ref) < 1e-8 * ref
     assert abs(f) < 1e-8
     assert it <= 8
@@ -48,9 +51,9 @@ def test_threshold_matches_oracle_bisection(twa, objective, target):
 
 def test_threshold_fp32_converges_to_the_fp64_root(twa):
     w32, f, it = twa.find_threshold(N_T, ALPHA_T, B_T, DT_T, T_T, SEED_T, objective="spsm_n", target=1.0, w_lo=1.0,
-                                    w_hi=2.0, tol_w=1e-6, precision="fp32", burnin=BURN_T)
+                                    w_hi=2.0, tol_w=1e-6, precision="fp32", burnin=BURN_T, norm_tol=-1)
     w64, _, _ = twa.find_threshold(N_T, ALPHA_T, B_T, DT_T, T_T, SEED_T, objective="spsm_n", target=1.0, w_lo=1.0,
-                                   w_hi=2.0, tol_w=1e-10, precision="fp64", burnin=BURN_T)
+                                   w_hi=2.0, tol_w=1e-10, precision="fp64", burnin=BURN_T, norm_tol=-1)
     assert abs(f) < 1e-5 and it <= 10
     assert abs(w32 - w64) < 1e-4 * w64
 
@@ -58,13 +61,13 @@ def test_threshold_fp32_converges_to_the_fp64_root(twa):
 def test_threshold_rejects_bracket_without_crossing(twa):
     with pytest.raises(twa.TWAError) as e:
         twa.find_threshold(N_T, ALPHA_T, 64, DT_T, 100, 0, objective="spsm_n", target=100.0, w_lo=1.0, w_hi=2.0,
-                           precision="fp64")
+                           precision="fp64", norm_tol=-1)
     assert e.value.code == -6
 
 
 def test_g2_min_scan_matches_oracle(twa):
     N, alpha, B, wts = 8, 1.5, 128, [0.4, 0.7, 1.0]
-    wt, g2, wmin, gmin = twa.g2_min(N, alpha, B, seed=2, n_points=3, wt_lo=0.4, wt_hi=1.0, precision="fp64")
+    wt, g2, wmin, gmin = twa.g2_min(N, alpha, B, seed=2, n_points=3, wt_lo=0.4, wt_hi=1.0, precision="fp64", norm_tol=-1)
     ref = oprot.g2_scan(N, alpha, B, wts, seed=2)
     assert np.allclose(wt, wts, rtol=0, atol=1e-15)
     assert np.max(np.abs(g2 - ref) / ref) < 1e-9, (g2, ref)
