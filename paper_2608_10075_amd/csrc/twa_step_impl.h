@@ -31,11 +31,6 @@
 #include "twa_internal.h"
 #include "twa_device.h"
 
-// Prefetch distance of the 320 x 256 tiles, in K stages (0: off)
-#ifndef TWA_PF_DIST
-#define TWA_PF_DIST 0
-#endif
-
 namespace twa {
 
 template <int PREC>
@@ -490,34 +485,7 @@ __device__ __forceinline__ void stage_tile(const GemmArgs<PREC>& a, const int mt
         }
         __syncthreads();   // the sums are visible to every wave; red is free again
     }
-    // L2 prefetch PFD stages ahead (two-stage rings only): one 4-byte
-    // global->LDS load per lane touches the cache line of one operand row of a
-    // later stage, so that the ring's own loads of that stage hit L2 instead
-    // of waiting out a full HBM round trip behind a one-stage lead.  Every wave
-    // issues exactly one such load per stage (lanes past the last row repeat
-    // a row), so the vmcnt accounting is the same in every wave.  The touched
-    // data land in `red`, which the loop does not use: the last stage waits
-    // for every load (vmcnt 0) before the epilogue writes it.
-    constexpr int PFD = (NST == 2 && MT == 320 && NT == 256) ? TWA_PF_DIST : 0;
-    static_assert(PFD == 0 || sizeof(red) >= (size_t)NWV * 256, "prefetch landing area");
-    static_assert(PFD == 0 || KB == 128, "one cache line per row and stage");
-    const char* pf_src = nullptr;
-    if constexpr (PFD > 0) {
-        const int r = (wv * 64 + lane) % (MT + NT);
-        pf_src = r < MT ? Ag + r * lda_b : Xg + (int64_t)(r - MT) * ldx_b;
-    }
-#define TWA_PREFETCH(KT_)                                                                                      \
-    __builtin_amdgcn_global_load_lds((gptr_t*)(pf_src + (int64_t)(KT_) * KB),                                 \
-                                     (lds_t*)(reinterpret_cast<char*>(&red[0][0][0]) + wv * 256), 4, 0, 0)
-    // prologue: stages 0 .. NST-2 in flight.  With the prefetch, iteration kt
-    // touches stage kt + PFD right after loading stage kt + 1, and the
-    // prologue touches stages 2 .. PFD-1 before loading stage 0 (so the first
-    // wait covers them)
-    if constexpr (PFD > 0) {
-#pragma unroll
-        for (int u = 2; u < PFD; ++u)
-            if (u < nk) TWA_PREFETCH(u);
-    }
+    // prologue: stages 0 .. NST-2 in flight
 #pragma unroll
     for (int u = 0; u < NST - 1; ++u)
         if (u < nk) TWA_DMA(u, TWA_BUF(u));
@@ -527,16 +495,9 @@ __device__ __forceinline__ void stage_tile(const GemmArgs<PREC>& a, const int mt
             const int kt = kt0 + u;
             if (kt < nk) {
                 // stage kt has landed once at most the later stages are pending
-                // (waves that load fewer chunks per stage wait conservatively);
-                // with the prefetch, the one touch issued after stage kt's loads
-                // may still be in flight
-                if constexpr (PFD > 0) {
-                    if (kt > 0 && kt + PFD - 1 < nk) TWA_WAIT_VM(1);
-                    else TWA_WAIT_VM(0);
-                } else {
-                    if (nk - 1 - kt >= NST - 2) TWA_WAIT_VM((NST - 2) * CPWMIN);
-                    else TWA_WAIT_VM(0);
-                }
+                // (waves that load fewer chunks per stage wait conservatively)
+                if (nk - 1 - kt >= NST - 2) TWA_WAIT_VM((NST - 2) * CPWMIN);
+                else TWA_WAIT_VM(0);
                 // Barrier without a memory fence: a fence would wait for every
                 // load still in flight into the later stages.  What it has to
                 // order is covered explicitly: this wave's loads into stage kt
@@ -545,9 +506,6 @@ __device__ __forceinline__ void stage_tile(const GemmArgs<PREC>& a, const int mt
                 __builtin_amdgcn_s_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
                 if (kt + NST - 1 < nk) TWA_DMA(kt + NST - 1, TWA_BUF((u + NST - 1) % NST));
-                if constexpr (PFD > 0) {
-                    if (kt + PFD < nk) TWA_PREFETCH(kt + PFD);
-                }
                 __builtin_amdgcn_sched_barrier(0);
                 if constexpr (QSNAP) {
                     if (kt == a.kq) {
@@ -562,7 +520,6 @@ __device__ __forceinline__ void stage_tile(const GemmArgs<PREC>& a, const int mt
         }
     }
 #undef TWA_DMA
-#undef TWA_PREFETCH
 #undef TWA_COMPUTE
 #undef TWA_BUF
 #undef TWA_WAIT_VM
