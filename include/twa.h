@@ -318,6 +318,26 @@ typedef struct twa_outputs {
 TWA_API int twa_run(const twa_params* p, int64_t n_traj, double dt, int64_t n_steps,
                     uint64_t seed, twa_observables* out, const twa_outputs* outs);
 
+/*
+ * twa_run_noalloc -- twa_run for callers that cannot allocate device memory:
+ * code under hipGraph stream capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  It calls no allocating routine: every buffer of the run
+ * is carved from a file-scope device array of TWA_NOALLOC_SCRATCH_BYTES that
+ * each device holds until the process ends (its address taken once per
+ * device), and the jackknife block sums are formed on the device.  Same
+ * kernels and results as twa_run (bit for bit) for: a pump from
+ * twa_build_pump or twa_build_pump_dense, Heun or the semi-implicit scheme,
+ * any precision, n_lags = 0, no init_state; no hipGraph replay and no timing
+ * (kernel_ms is NaN).  The caller passes the stream (NULL = null stream).
+ * Calls that overlap on one device share the array and race: serialise them.
+ * Errors: TWA_EINVAL (as twa_run, and for the unsupported options above),
+ *         TWA_ENOMEM (the run's buffers exceed the scratch size; the message
+ *         states the bytes needed), TWA_EHIP, TWA_EUNSTABLE.
+ */
+#define TWA_NOALLOC_SCRATCH_BYTES (64u << 20)
+TWA_API int twa_run_noalloc(const twa_params* p, int64_t n_traj, double dt, int64_t n_steps, uint64_t seed,
+                            twa_observables* out);
+
 /* ======================================================================
  * Batched phase-diagram scan: many independent (N, w, alpha) points.
  * ====================================================================== */

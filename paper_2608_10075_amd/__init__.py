@@ -115,6 +115,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.twa_run_batch.argtypes = [C.POINTER(_Point), C.c_int, C.POINTER(_BatchOpts), C.POINTER(_Obs)]
     lib.twa_adjoint.argtypes = [C.POINTER(_Params), C.c_int64, C.c_double, C.c_int64, C.c_uint64, C.c_int32,
                                 C.POINTER(_Obs), C.POINTER(C.c_double)]
+    lib.twa_run_noalloc.argtypes = [C.POINTER(_Params), C.c_int64, C.c_double, C.c_int64, C.c_uint64,
+                                    C.POINTER(_Obs)]
     lib.twa_tangent_w.argtypes = [C.POINTER(_Params), C.c_int64, C.c_double, C.c_int64, C.c_uint64,
                                   C.POINTER(_Obs), C.POINTER(C.c_double)]
     lib.twa_philox.argtypes = [P, C.c_int64, C.c_uint32, C.c_uint32, P, P]
@@ -129,7 +131,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
                                C.c_double, C.c_double, C.c_double, C.c_int32, C.POINTER(C.c_double),
                                C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double)]
     for name in ("twa_build_pump", "twa_build_pump_dense", "twa_build_pump_toeplitz", "twa_build_model_dense", "twa_pump_info", "twa_pump_copy_matrix", "twa_run",
-                 "twa_run_batch", "twa_adjoint", "twa_tangent_w", "twa_philox", "twa_noise", "twa_protocol", "twa_find_threshold",
+                 "twa_run_batch", "twa_adjoint", "twa_tangent_w", "twa_run_noalloc", "twa_philox", "twa_noise", "twa_protocol", "twa_find_threshold",
                  "twa_g2_min"):
         getattr(lib, name).restype = C.c_int
     return lib
@@ -309,6 +311,22 @@ def run(pump: Pump, n_traj: int, dt: float, n_steps: int, seed: int = 0, *, gamm
     res.obs = _obs_dict(o)
     res.n_blocks = nb.value
     return res
+
+
+def run_noalloc(pump: Pump, n_traj: int, dt: float, n_steps: int, seed: int = 0, *, gamma: float = 1.0,
+                s0z: float = 1.0, burnin: int = -1, precision: str = "fp32", point: int = 0, tile_config: int = -1,
+                integrator: str = "heun", stream=None, norm_tol: float = 0.0, allow_unstable: bool = False) -> dict:
+    """twa_run_noalloc: the observables of twa_run for a run whose buffers fit
+    the library's fixed device scratch array (no device allocation)."""
+    p = _base_params(gamma, s0z, burnin, precision, point, tile_config, stream, norm_tol)
+    p.pump = pump.handle
+    p.integrator = INTEGRATORS[integrator]
+    o = _Obs()
+    rc = _lib.twa_run_noalloc(C.byref(p), int(n_traj), float(dt), int(n_steps), C.c_uint64(seed & (2 ** 64 - 1)),
+                              C.byref(o))
+    if not (rc == TWA_EUNSTABLE and allow_unstable):
+        _check(rc)
+    return _obs_dict(o)
 
 
 def run_batch(points, n_traj: int, n_steps: int, *, burnin: int = -1, gamma: float = 1.0, s0z: float = 1.0,

@@ -59,6 +59,10 @@ void free_buffers(EnsembleBuffers& b);
 int alloc_buffers(const Geometry& g, bool tangents, int64_t L, int J, EnsembleBuffers& b);
 Geometry make_geometry(int precision, int cfg, int64_t N, int64_t B);
 void finalize_moments(const std::vector<double>& traj, int64_t B, twa_observables* o);
+// the same from the jackknife block sums bsum [J][5] of the per-trajectory
+// window averages (trajectory k in block k J / B, summed in k order) and the
+// block sizes bcnt [J]; J <= 32, no allocation
+void finalize_blocks(const double* bsum, const double* bcnt, int J, int64_t B, twa_observables* o);
 void finalize_decay(const std::vector<double>& traj, int64_t B, twa_observables* o);
 double linewidth_of(const std::vector<std::complex<double>>& corr, double tau);
 // two-time finalisation: lag sums hlag [L][J][6] (block sums of the symmetric
@@ -76,6 +80,8 @@ int launch_step_kernels(const Geometry& g, EnsembleBuffers& b, const StepConsts&
                         GemmTimers* tm, hipStream_t st);
 int run_single(const twa_params* p, int64_t n_traj, double dt, int64_t n_steps, uint64_t seed,
                twa_observables* out, const twa_outputs* outs);
+int run_noalloc(const twa_params* p, int64_t n_traj, double dt, int64_t n_steps, uint64_t seed,
+                twa_observables* out);
 int run_tangent_w(const twa_params* p, int64_t n_traj, double dt, int64_t n_steps, uint64_t seed,
                   twa_observables* out, double* grads);
 

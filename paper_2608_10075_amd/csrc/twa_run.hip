@@ -58,12 +58,16 @@ int pick_tile_cfg(int precision, int64_t N, int64_t n_traj) {
 void finalize_moments(const std::vector<double>& traj, int64_t B, twa_observables* o) {
     // traj: [B][5] per-trajectory window averages
     const int J = (int)std::min<int64_t>(32, B);
-    std::vector<double> bsum((size_t)J * 5, 0.0), bcnt((size_t)J, 0.0);
+    double bsum[32 * 5] = {0}, bcnt[32] = {0};
     for (int64_t k = 0; k < B; ++k) {
         const int j = (int)((k * J) / B);
         for (int m = 0; m < 5; ++m) bsum[(size_t)j * 5 + m] += traj[(size_t)k * 5 + m];
         bcnt[(size_t)j] += 1.0;
     }
+    finalize_blocks(bsum, bcnt, J, B, o);
+}
+
+void finalize_blocks(const double* bsum, const double* bcnt, int J, int64_t B, twa_observables* o) {
     double tot[5] = {0, 0, 0, 0, 0};
     for (int j = 0; j < J; ++j)
         for (int m = 0; m < 5; ++m) tot[m] += bsum[(size_t)j * 5 + m];
@@ -80,7 +84,7 @@ void finalize_moments(const std::vector<double>& traj, int64_t B, twa_observable
     derive(mean, mean + 5);
     double se[8];
     if (J >= 2) {
-        std::vector<double> vals((size_t)J * 8);
+        double vals[32 * 8];
         for (int j = 0; j < J; ++j) {
             double* v = &vals[(size_t)j * 8];
             for (int m = 0; m < 5; ++m) v[m] = (tot[m] - bsum[(size_t)j * 5 + m]) / ((double)B - bcnt[(size_t)j]);
