@@ -494,23 +494,23 @@ int adjoint_impl(const twa_params* p, int64_t n_traj, double dt, int64_t n_steps
             bj.g = gj;
             TWA_TRY(launch_noise(g, bj, c, st));
             GemmCall p1;   // predictor, also storing its noise part Q = -sqrt(dt) F zeta (second K half)
-            p1.kind = KIND_PRIMAL_WITH_Q; p1.stage = 1; p1.A = b.A; p1.lda = 2 * g.P; p1.X = b.Xop;
+            p1.kind = KIND_PRIMAL_WITH_Q; p1.stage = 1; p1.A = b.A; p1.X = b.Xop;
             p1.ldx = 2 * g.P; p1.K = 2 * g.P;
             p1.c1 = c.c1; p1.c2 = c.c2; p1.s_cur = sj; p1.dlt = dj; p1.Y = y1j; p1.Dop = b.Dop; p1.Sout = qj;
             p1.part_prim = pSj; p1.part_out = pPj; p1.g = gj; p1.step = b.step;
             TWA_TRY(launch_gemm_call(g, p1, st));
             GemmCall sa1;  // dY1/dalpha = A_alpha [s; zeta]
-            sa1.kind = 2; sa1.stage = 1; sa1.A = m.Aa; sa1.lda = 2 * g.P; sa1.X = b.Xop; sa1.ldx = 2 * g.P;
+            sa1.kind = 2; sa1.stage = 1; sa1.A = m.Aa; sa1.X = b.Xop; sa1.ldx = 2 * g.P;
             sa1.K = 2 * g.P; sa1.Sout = ya1j; sa1.store_sign = 1.0;
             TWA_TRY(launch_gemm_call(g, sa1, st));
             GemmCall p2;
-            p2.kind = 0; p2.stage = 2; p2.A = b.A; p2.lda = 2 * g.P; p2.X = b.Dop; p2.ldx = g.P; p2.K = g.P;
+            p2.kind = 0; p2.stage = 2; p2.A = b.A; p2.X = b.Dop; p2.ldx = g.P; p2.K = g.P;
             p2.c1 = c.c1; p2.c2 = c.c2; p2.s_cur = sj; p2.s_next = sj1; p2.dlt = dj; p2.Y = y1j; p2.Y2out = y2j;
             p2.store_y2 = 1; p2.part_prim = pPj; p2.part_out = pSj1; p2.Xnext = b.Xop; p2.ldxn = 2 * g.P; p2.g = gj;
             p2.step = b.step;
             TWA_TRY(launch_gemm_call(g, p2, st));
             GemmCall sa2;  // dY2/dalpha = dY1/dalpha + A_alpha,left D
-            sa2.kind = 2; sa2.stage = 1; sa2.A = m.Aa; sa2.lda = 2 * g.P; sa2.X = b.Dop; sa2.ldx = g.P; sa2.K = g.P;
+            sa2.kind = 2; sa2.stage = 1; sa2.A = m.Aa; sa2.X = b.Dop; sa2.ldx = g.P; sa2.K = g.P;
             sa2.Sin = ya1j; sa2.Sout = ya2j; sa2.store_sign = 1.0;
             TWA_TRY(launch_gemm_call(g, sa2, st));
         }
@@ -529,14 +529,14 @@ int adjoint_impl(const twa_params* p, int64_t n_traj, double dt, int64_t n_steps
             char* gj = (char*)m.g + (size_t)j * 2 * g.Bp * se;
             TWA_TRY(prep_nu2<PREC>(g, m.lam, sj, dj, m.nu2, m.nu2p, nobj, st));
             GemmCall a2;
-            a2.kind = 3; a2.stage = 2; a2.ncopy = nobj; a2.A = b.A; a2.lda = 2 * g.P; a2.X = m.nu2; a2.ldx = g.P;
+            a2.kind = 3; a2.stage = 2; a2.ncopy = nobj; a2.A = b.A; a2.X = m.nu2; a2.ldx = g.P;
             a2.x_copy = g.C2 * g.P; a2.K = g.P; a2.c1 = c.c1; a2.c2 = c.c2; a2.s_cur = sj; a2.dlt = dj; a2.Y = y1j;
             a2.Y2in = y2j; a2.Qin = qj; a2.YA = ya2j; a2.lam = m.lam; a2.M1 = m.M1; a2.Rb = m.Rb;
             a2.part_prim = pPj; a2.g = gj; a2.tpart_in = m.nu2p; a2.part_out = m.nu1p; a2.Xnext = m.nu1;
             a2.ldxn = g.P; a2.gacc = m.gacc; a2.inv_w = 1.0 / pump->w;
             TWA_TRY(launch_gemm_call(g, a2, st));
             GemmCall a1;
-            a1.kind = 4; a1.stage = 1; a1.ncopy = nobj; a1.A = b.A; a1.lda = 2 * g.P; a1.X = m.nu1; a1.ldx = g.P;
+            a1.kind = 4; a1.stage = 1; a1.ncopy = nobj; a1.A = b.A; a1.X = m.nu1; a1.ldx = g.P;
             a1.x_copy = g.C2 * g.P; a1.K = g.P; a1.c1 = c.c1; a1.c2 = c.c2; a1.s_cur = sj; a1.Y = y1j; a1.Qin = qj;
             a1.YA = ya1j; a1.lam = m.lam; a1.M1 = m.M1; a1.Rb = m.Rb; a1.part_prim = pSj; a1.g = gj;
             a1.tpart_in = m.nu1p; a1.gacc = m.gacc; a1.inv_w = 1.0 / pump->w;

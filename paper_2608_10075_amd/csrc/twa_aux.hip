@@ -17,11 +17,12 @@ struct P_ {
 
 static inline unsigned nblocks(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
-// A = [-dt/2 W | -sqrt(dt) F], zero padded to [P][2P]; in the split form
-// [P][6P] = [Wh | Wh | Wl | Fh | Fh | Fl] against operand columns
-// (sh, sl, sh, zh, zl, zh)
+// A = [-dt/2 W | -sqrt(dt) F], zero padded to P rows and 2P columns; in the
+// split form 6P columns [Wh | Wh | Wl | Fh | Fh | Fl] against operand columns
+// (sh, sl, sh, zh, zl, zh); stored stage-blocked (a_index) with kt columns
+// per block
 template <int PREC>
-__global__ void build_A_kernel(const double* W, const double* F, int64_t N, int64_t P, double cw,
+__global__ void build_A_kernel(const double* W, const double* F, int64_t N, int64_t P, int64_t kt, double cw,
                                double cf, typename Prec<PREC>::G* A) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= P * 2 * P) return;
@@ -34,19 +35,19 @@ __global__ void build_A_kernel(const double* W, const double* F, int64_t N, int6
     if constexpr (Prec<PREC>::SPLIT == 3) {
         uint16_t hi, lo;
         bf16_split((float)v, hi, lo);
-        typename Prec<PREC>::G* row = A + i * 6 * P + (j < P ? j : 3 * P + (j - P));
-        row[0].v = hi;
-        row[P].v = hi;
-        row[2 * P].v = lo;
+        const int64_t c = j < P ? j : 3 * P + (j - P);
+        A[a_index(i, c, P, kt)].v = hi;
+        A[a_index(i, c + P, P, kt)].v = hi;
+        A[a_index(i, c + 2 * P, P, kt)].v = lo;
     } else {
-        A[t] = Prec<PREC>::to_g((typename Prec<PREC>::S)v);
+        A[a_index(i, j, P, kt)] = Prec<PREC>::to_g((typename Prec<PREC>::S)v);
     }
 }
 
 template <int PREC>
 static int build_A_t(const Geometry& g, const double* W, const double* F, double dt, void* A, hipStream_t st) {
     const int64_t n = g.P * 2 * g.P;
-    hipLaunchKernelGGL(build_A_kernel<PREC>, dim3(nblocks(n, 256)), dim3(256), 0, st, W, F, g.N, g.P,
+    hipLaunchKernelGGL(build_A_kernel<PREC>, dim3(nblocks(n, 256)), dim3(256), 0, st, W, F, g.N, g.P, g.kt,
                        -0.5 * dt, -sqrt(dt), static_cast<typename Prec<PREC>::G*>(A));
     TWA_HIP_CHECK(hipGetLastError());
     return TWA_OK;
@@ -70,10 +71,11 @@ int launch_build_A(const Geometry& g, const double* W, const double* F, double d
 // coherent exchange: A = [-dt/2 W | -sqrt(dt) F | dt Omega] against operand
 // columns (s, zeta, s_perp), and the corrector's A2 = [-dt/2 W | dt Omega]
 // against (D, D_perp), s_perp = (s^y, -s^x) for the (x, y) columns: the field
-// of Eq. (S1) gains +dt (Omega s^y) in h^x and -dt (Omega s^x) in h^y
+// of Eq. (S1) gains +dt (Omega s^y) in h^x and -dt (Omega s^x) in h^y; both
+// stored stage-blocked (a_index)
 template <int PREC>
 __global__ void build_A_coh_kernel(const double* W, const double* F, const double* Om, int64_t N, int64_t P,
-                                   double cw, double cf, double co, typename Prec<PREC>::G* A,
+                                   int64_t kt, double cw, double cf, double co, typename Prec<PREC>::G* A,
                                    typename Prec<PREC>::G* A2) {
     typedef typename Prec<PREC>::S S;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -85,8 +87,8 @@ __global__ void build_A_coh_kernel(const double* W, const double* F, const doubl
         const double m = blk == 0 ? W[i * N + jj] : blk == 1 ? F[i * N + jj] : Om[i * N + jj];
         v = (blk == 0 ? cw : blk == 1 ? cf : co) * m;
     }
-    A[t] = Prec<PREC>::to_g((S)v);
-    if (blk != 1) A2[i * 2 * P + (blk == 0 ? jj : P + jj)] = Prec<PREC>::to_g((S)v);
+    A[a_index(i, j, P, kt)] = Prec<PREC>::to_g((S)v);
+    if (blk != 1) A2[a_index(i, blk == 0 ? jj : P + jj, P, kt)] = Prec<PREC>::to_g((S)v);
 }
 
 template <int PREC>
@@ -98,7 +100,7 @@ static int build_A_coh_t(const Geometry& g, const double* W, const double* F, co
     } else {
         const int64_t n = g.P * 3 * g.P;
         hipLaunchKernelGGL(build_A_coh_kernel<PREC>, dim3(nblocks(n, 256)), dim3(256), 0, st, W, F, Om, g.N, g.P,
-                           -0.5 * dt, -sqrt(dt), dt, static_cast<typename Prec<PREC>::G*>(A),
+                           g.kt, -0.5 * dt, -sqrt(dt), dt, static_cast<typename Prec<PREC>::G*>(A),
                            static_cast<typename Prec<PREC>::G*>(A2));
         TWA_HIP_CHECK(hipGetLastError());
         return TWA_OK;

@@ -22,18 +22,18 @@ namespace {
 
 inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
-// observation operands: G and G o G zero padded to [P][P] in the contraction
-// type, and the diagonal of G in the state type
+// observation operands: G and G o G zero padded to P x P in the contraction
+// type, stored stage-blocked (a_index), and the diagonal of G in the state type
 template <int PREC>
-__global__ void decay_ops_kernel(const double* G, int64_t N, int64_t P, typename Prec<PREC>::G* AG,
+__global__ void decay_ops_kernel(const double* G, int64_t N, int64_t P, int64_t kt, typename Prec<PREC>::G* AG,
                                  typename Prec<PREC>::G* AGG, typename Prec<PREC>::S* dg) {
     typedef typename Prec<PREC>::S S;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= P * P) return;
     const int64_t i = t / P, j = t % P;
     const double v = (i < N && j < N) ? G[i * N + j] : 0.0;
-    AG[t] = Prec<PREC>::to_g((S)v);
-    AGG[t] = Prec<PREC>::to_g((S)(v * v));
+    AG[a_index(i, j, P, kt)] = Prec<PREC>::to_g((S)v);
+    AGG[a_index(i, j, P, kt)] = Prec<PREC>::to_g((S)(v * v));
     if (i == j) dg[i] = (S)v;
 }
 
@@ -105,7 +105,7 @@ template <int PREC>
 int build_ops_t(const Geometry& g, const double* G, const EnsembleBuffers& b, hipStream_t st) {
     typedef typename Prec<PREC>::G GT;
     typedef typename Prec<PREC>::S S;
-    hipLaunchKernelGGL(decay_ops_kernel<PREC>, dim3(nblk(g.P * g.P, 256)), dim3(256), 0, st, G, g.N, g.P,
+    hipLaunchKernelGGL(decay_ops_kernel<PREC>, dim3(nblk(g.P * g.P, 256)), dim3(256), 0, st, G, g.N, g.P, g.kt,
                        static_cast<GT*>(b.AG), static_cast<GT*>(b.AGG), static_cast<S*>(b.dg));
     TWA_HIP_CHECK(hipGetLastError());
     return TWA_OK;
@@ -121,7 +121,6 @@ int observe_t(const Geometry& g, const EnsembleBuffers& b, int cur, hipStream_t 
     c.kind = 2;
     c.stage = 1;
     c.A = b.AG;
-    c.lda = g.P;
     c.X = b.Xop;
     c.ldx = (2 + g.coh) * g.P;   // the state block leads every operand column
     c.K = g.P;
@@ -139,7 +138,6 @@ int observe_t(const Geometry& g, const EnsembleBuffers& b, int cur, hipStream_t 
     u.kind = 2;
     u.stage = 1;
     u.A = b.AGG;
-    u.lda = g.P;
     u.X = b.Zop;
     u.ldx = g.P;
     u.K = g.P;

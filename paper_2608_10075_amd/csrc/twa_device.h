@@ -9,6 +9,16 @@
 
 namespace twa {
 
+// The constant operand A of a contraction (P rows, K columns) is stored
+// stage-blocked: the kt columns of K stage q of all P rows are contiguous,
+// row after row, and the stages follow one another.  One LDS stage of MT rows
+// is then a single contiguous run of MT * kt elements (whole cache lines),
+// where a row-major matrix would give MT runs of kt elements one row pitch
+// apart.  kt = K elements per LDS stage of the tile configuration.
+__host__ __device__ __forceinline__ int64_t a_index(int64_t i, int64_t j, int64_t P, int64_t kt) {
+    return (j / kt) * P * kt + i * kt + (j % kt);
+}
+
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two 32x32
 // -> 64-bit multiplies with the published multipliers, the key advanced by

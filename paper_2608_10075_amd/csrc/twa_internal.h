@@ -114,8 +114,7 @@ struct StepConsts {
 constexpr int KIND_PRIMAL_WITH_Q = 0x100;
 struct GemmCall {
     int kind = 0, stage = 1, ncopy = 1;
-    const void* A = nullptr;
-    int64_t lda = 0;
+    const void* A = nullptr;        // P rows, stage-blocked (a_index, the geometry's kt)
     const void* X = nullptr;
     int64_t ldx = 0, x_copy = 0, K = 0;
     double c1 = 0, c2 = 0;

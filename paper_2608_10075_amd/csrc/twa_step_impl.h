@@ -37,8 +37,7 @@ template <int PREC>
 struct GemmArgs {
     typedef typename Prec<PREC>::G G;
     typedef typename Prec<PREC>::S S;
-    const G* A;
-    int64_t lda;        // elements
+    const G* A;         // P rows, stage-blocked with KB bytes per row and stage (a_index)
     const G* X;         // operand of copy 0
     int64_t ldx;
     int64_t x_copy;     // element offset between copies
@@ -340,9 +339,11 @@ __device__ __forceinline__ void stage_tile(const GemmArgs<PREC>& a, const int mt
 #pragma unroll
         for (int j = 0; j < BJ; ++j) acc[i][j] = AV{0, 0, 0, 0};
 
-    const char* Ag = reinterpret_cast<const char*>(a.A + m0 * a.lda);
+    // A is stage-blocked: row r of K stage q at byte (q P + r) KB; X columns
+    // are row-major with a pitch of ldx elements
+    const char* Ag = reinterpret_cast<const char*>(a.A) + m0 * KB;
     const char* Xg = reinterpret_cast<const char*>(a.X + cp * a.x_copy + n0 * a.ldx);
-    const int64_t lda_b = a.lda * (int64_t)sizeof(G), ldx_b = a.ldx * (int64_t)sizeof(G);
+    const int64_t ldx_b = a.ldx * (int64_t)sizeof(G);
     const int nk = (int)(a.K / KT);
     // Direct global -> LDS loads (global_load_lds_dwordx4): one wave
     // instruction moves 64 x 16 bytes into 1 KB of LDS, lane i to offset 16 i,
@@ -361,20 +362,23 @@ __device__ __forceinline__ void stage_tile(const GemmArgs<PREC>& a, const int mt
     };
     const int wv = __builtin_amdgcn_readfirstlane(wave);
     const char* src[CPW];
+    bool srcA[CPW];               // chunk j holds rows of A (else of X); wave-uniform
 #pragma unroll
     for (int j = 0; j < CPW; ++j) {
         const int q = wv + j * NWV < NCH ? wv + j * NWV : 0;
         const int row = q * RPC + lane / PCS;
         const int pc = (lane % PCS) ^ swz(row & 15);
-        src[j] = row < MT ? Ag + row * lda_b + pc * 16 : Xg + (int64_t)(row - MT) * ldx_b + pc * 16;
+        srcA[j] = q * RPC < MT;
+        src[j] = row < MT ? Ag + row * KB + pc * 16 : Xg + (int64_t)(row - MT) * ldx_b + pc * 16;
     }
+    const int64_t astage_b = P * KB;   // bytes between K stages of A
     typedef __attribute__((address_space(3))) char lds_t;
     typedef const __attribute__((address_space(1))) void gptr_t;
 #define TWA_DMA(KT_, BUF_)                                                                              \
     do {                                                                                                \
-        const int64_t kofs_ = (int64_t)(KT_) * KB;                                                      \
+        const int64_t kofs_ = (int64_t)(KT_) * KB, aofs_ = (int64_t)(KT_) * astage_b;                   \
         _Pragma("unroll") for (int j = 0; j < CPW; ++j) if (CPW == CPWMIN || wv + j * NWV < NCH)        \
-            __builtin_amdgcn_global_load_lds((gptr_t*)(src[j] + kofs_),                                 \
+            __builtin_amdgcn_global_load_lds((gptr_t*)(src[j] + (srcA[j] ? aofs_ : kofs_)),             \
                                              (lds_t*)((BUF_) + (wv + j * NWV) * 1024), 16, 0, 0);       \
     } while (0)
 
@@ -1156,7 +1160,6 @@ static GemmArgs<PREC> make_args(const Geometry& g, const EnsembleBuffers& b, con
     constexpr int SPL = Prec<PREC>::SPLIT;   // K blocks per value (split form: hi, lo, hi)
     const int64_t CK = g.coh ? 1 : 0;         // coherent exchange: one more K block (s_perp, D_perp)
     a.A = static_cast<const G*>(b.A);
-    a.lda = (2 + CK) * P * SPL;
     a.ldd = (1 + CK) * P * SPL;
     a.coh = g.coh;
     a.P = P;
@@ -1187,10 +1190,7 @@ static GemmArgs<PREC> make_args(const Geometry& g, const EnsembleBuffers& b, con
             a.part_prim = static_cast<const S*>(b.part[0]);
             a.part_out = static_cast<S*>(b.part[1]);
         } else {
-            if (CK) {   // corrector: [-dt/2 W | dt Omega] against (D, D_perp)
-                a.A = static_cast<const G*>(b.A2);
-                a.lda = 2 * P;
-            }
+            if (CK) a.A = static_cast<const G*>(b.A2);   // corrector: [-dt/2 W | dt Omega] against (D, D_perp)
             a.X = static_cast<const G*>(b.Dop);
             a.ldx = (1 + CK) * P * SPL;
             a.K = (1 + CK) * P * SPL;
@@ -1241,7 +1241,6 @@ int launch_call_p(const Geometry& g, const GemmCall& c, hipStream_t st) {
     typedef typename Prec<PREC>::S S;
     GemmArgs<PREC> a{};
     a.A = static_cast<const G*>(c.A);
-    a.lda = c.lda;
     a.X = static_cast<const G*>(c.X);
     a.ldx = c.ldx;
     a.x_copy = c.x_copy;
