@@ -179,6 +179,27 @@ def scan_points(n_points=96, seed=0):
     return pts
 
 
+def batch_singles(twa, steps, integrator="sib"):
+    """The 96 points of the scan one by one through the plain FP32 path only
+    (the single-run side of the batched comparison, for step counts where
+    both sides do not fit one run); device time of the step loops."""
+    pts = scan_points()
+    B = 512
+    single_ms = 0.0
+    for i, (N, w, a, dt, seed) in enumerate(pts):
+        p = twa.build_pump(N, w, a)
+        r = twa.run(p, B, dt, steps, seed=seed, point=i, precision="fp32", integrator=integrator)
+        single_ms += r.obs["kernel_ms"]
+        p.close()
+        print("[bench]   single run %d/%d (N = %d): %.1f ms" % (i + 1, len(pts), N, r.obs["kernel_ms"]),
+              file=sys.stderr, flush=True)
+    work = sum(B * N * steps for (N, _, _, _, _) in pts)
+    flops = sum(12.0 * N * N * B * steps for (N, _, _, _, _) in pts)
+    return {"points": len(pts), "n_traj": B, "steps": steps, "precision": "fp32", "integrator": integrator,
+            "single_runs_ms": single_ms, "single_rate": work / (single_ms * 1e-3), "unit": "trajectory-atom-steps/s",
+            "single_tflops": flops / (single_ms * 1e-3) / 1e12}
+
+
 def batch_scan(twa, steps, integrator="sib", singles=True):
     """Batched scan (grouped persistent launches, graph replay, autotuned
     tiles) against the same 96 points run one by one through the plain FP32
@@ -449,6 +470,8 @@ def main():
                     help="also time the 96-point scan for this many steps")
     ap.add_argument("--batch-singles", action="store_true",
                     help="with --batch-scan: also run the 96 points one by one (dense and Toeplitz)")
+    ap.add_argument("--batch-singles-only", type=int, default=0,
+                    help="run only the 96 points one by one (dense FP32) for this many steps")
     ap.add_argument("--copy-calibration", action="store_true", help="one 1 GiB device copy, then exit")
     ap.add_argument("--toeplitz-only", action="store_true", help="the Toeplitz profiling workload, then exit")
     args = ap.parse_args()
@@ -564,6 +587,9 @@ def main():
     if args.batch_scan > 0:
         print("[bench] batched scan, 96 points, %d steps" % args.batch_scan, file=sys.stderr, flush=True)
         line["batch_scan"] = batch_scan(twa, args.batch_scan, singles=args.batch_singles)
+    if args.batch_singles_only > 0:
+        print("[bench] the 96 scan points one by one, %d steps" % args.batch_singles_only, file=sys.stderr, flush=True)
+        line["batch_singles"] = batch_singles(twa, args.batch_singles_only)
     if not args.no_adjoint:
         print("[bench] adjoint cost ratio (N=2000, FP32)", file=sys.stderr, flush=True)
         line["adjoint"] = adjoint_cost(twa)
