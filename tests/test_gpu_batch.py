@@ -4,6 +4,7 @@ C ABI: every point against the FP64 oracle per trajectory (window moments,
 final states and two-time block sums), every point against its own single
 run bit for bit, graph replay against direct launches, and the autotuner's
 per-bucket cache."""
+import functools
 import os
 
 import numpy as np
@@ -39,8 +40,11 @@ def _points(n, seed=0, nmin=40, nmax=400):
 
 # one point in each N bucket (<= 128, <= 1024, larger), ragged sizes
 ORACLE_POINTS = [(70, 1.0, 0.5, 2e-4, 11), (300, 2.0, 1.0, 6e-5, 12), (1100, 3.0, 1.5, 2e-5, 13)]
+# and the upper end of the scan's N range in the large-N bucket
+ORACLE_POINTS_WIDE = ORACLE_POINTS + [(4096, 1.5, 2.0, 5e-6, 14)]
 
 
+@functools.lru_cache(maxsize=None)
 def _oracle(pt, index, B, T, burnin, **kw):
     N, w, a, dt, seed = pt
     cfg = otwa.RunConfig(n_spin=N, w=w, alpha=a, n_traj=B, dt=dt, n_steps=T, seed=seed, point=index,
@@ -51,13 +55,14 @@ def _oracle(pt, index, B, T, burnin, **kw):
 @pytest.mark.parametrize("prec,tile,tol", [("fp64", -1, 1e-10), ("fp32", -1, 1e-5), ("fp32", 7, 1e-5),
                                            ("fp32", 2, 1e-5)])
 def test_batch_points_match_oracle(twa, prec, tile, tol):
-    """Each point of a batch spanning the three N buckets against the FP64
-    oracle per trajectory: window moments T2 ... ZZ and final states
-    (tile -1: autotuned per bucket; 7: the 320x256 tiles for every point)."""
+    """Each point of a batch spanning the three N buckets and reaching the
+    scan's largest N against the FP64 oracle per trajectory: window moments
+    T2 ... ZZ and final states (tile -1: autotuned per bucket; 7 and 2: those
+    tiles for every point)."""
     B, T, burn = 40, 40, 20
-    res = twa.run_batch(ORACLE_POINTS, B, T, burnin=burn, precision=prec, tile_config=tile, want_traj=True,
+    res = twa.run_batch(ORACLE_POINTS_WIDE, B, T, burnin=burn, precision=prec, tile_config=tile, want_traj=True,
                         want_final_state=True, norm_tol=-1)
-    for i, (pt, r) in enumerate(zip(ORACLE_POINTS, res)):
+    for i, (pt, r) in enumerate(zip(ORACLE_POINTS_WIDE, res)):
         ref = _oracle(pt, i, B, T, burn)
         if tile >= 0:
             assert r.obs["tile_config"] == tile

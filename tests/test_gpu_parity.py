@@ -94,7 +94,7 @@ def test_fp32_trajectories_1e3_steps(twa, N, B, cfg):
     """FP32 per-trajectory parity at fixed noise over 1e3 steps: 1e-5 relative,
     at a step meeting the paper's criterion max(Gamma N, w_max) dt < 0.05."""
     w, alpha, seed = 2.0, 1.0, 5
-    T = 1000 if N < 600 else 300     # keeps the oracle within seconds at the larger tiles
+    T = 1000
     dt = 0.02 / N
     p = twa.build_pump(N, w, alpha)
     r = twa.run(p, B, dt, T, seed=seed, precision="fp32", tile_config=cfg, want_final_state=True, norm_tol=-1)

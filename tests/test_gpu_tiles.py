@@ -39,6 +39,8 @@ TWO_TIME_CASES = [
     ("fp32", 2, 300, 70, 1e-5),
     ("fp32", 7, 650, 130, 1e-5),
     ("fp32", 8, 650, 130, 1e-5),
+    ("fp32", 7, 1000, 64, 1e-5),
+    ("fp32", 1, 100, 40, 1e-5),
 ]
 
 
