@@ -291,10 +291,15 @@ typedef struct twa_outputs {
 /*
  * twa_run -- integrate n_traj independent trajectories of Eq. (S1) for
  * n_steps steps of size dt and accumulate the observables.
- *   Noise: Philox4x32-10 keyed by `seed` (counter layout documented with the
- *   oracle and in the design notes); xi^a dt -> sqrt(Gamma dt) g^a (one
- *   collective normal pair per trajectory and step), chi^a dt ->
- *   sqrt(dt) F zeta^a (N normal pairs per trajectory and step).
+ *   Noise: Philox4x32-10 with key (seed low word, seed high word) and
+ *   counter (c0, c1, c2, c3), c3 = tag | (point << 8); Box-Muller turns each
+ *   pair of words into a pair of normals.  Step n (0-based), trajectory k:
+ *   zeta^x, zeta^y of spin 2m from words (0, 1) and of spin 2m+1 from words
+ *   (2, 3) of counter (m, k, n, tag 0); g^x, g^y from words (0, 1) of
+ *   (0, k, n, tag 1).  xi^a dt -> sqrt(Gamma dt) g^a (one collective normal
+ *   pair per trajectory and step), chi^a dt -> sqrt(dt) F zeta^a (N normal
+ *   pairs per trajectory and step).  Initial signs of s^x_i, s^y_i: bits
+ *   2j, 2j+1 (j = i mod 64) of counter (i / 64, k, 0, tag 2).
  *   Integrator: stochastic Heun (Euler predictor, trapezoidal corrector with
  *   the same noise increments).
  *   Window: states after steps burnin+1 .. n_steps are averaged.
@@ -320,8 +325,12 @@ TWA_API int twa_run(const twa_params* p, int64_t n_traj, double dt, int64_t n_st
 
 /*
  * twa_run_noalloc -- twa_run for callers that cannot allocate device memory:
- * code under hipGraph stream capture, tight serving loops, harnesses that
- * forbid hipMalloc.  It calls no allocating routine: every buffer of the run
+ * tight serving loops, harnesses that forbid hipMalloc, processes whose
+ * device memory another allocator owns.  It calls no allocating routine
+ * (hipMalloc, hipFree or a library routine that allocates); it does end
+ * with a copy of the scalar results to the host and a synchronisation of
+ * the caller's stream, so it cannot itself be recorded under hipGraph
+ * stream capture (call it outside a capture).  Every buffer of the run
  * is carved from a file-scope device array of TWA_NOALLOC_SCRATCH_BYTES that
  * each device holds until the process ends (its address taken once per
  * device), and the jackknife block sums are formed on the device.  Same

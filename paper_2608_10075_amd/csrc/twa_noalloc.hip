@@ -1,6 +1,8 @@
 // twa_run_noalloc: twa_run for callers that cannot allocate device memory
-// (code under hipGraph capture, tight serving loops, harnesses that forbid
-// allocation).  Every buffer of the run is carved from one file-scope device
+// (tight serving loops, harnesses that forbid allocation).  It ends with a
+// copy of the results to the host and a synchronisation of the caller's
+// stream, so it is not itself capturable into a hipGraph.  Every buffer of
+// the run is carved from one file-scope device
 // array of fixed size, `scratch`; the kernels are those of twa_run, so the
 // results are the same bit for bit.  The per-trajectory window averages are
 // reduced to jackknife block sums on the device, so the host side needs no
