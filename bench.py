@@ -137,13 +137,16 @@ def adjoint_cost(twa, steps=2048, reps=1):
         r = twa.run(pump, B, dt, steps, seed=0, precision="fp32", norm_tol=-1)
         torch.cuda.synchronize()
         t1 = time.time()
+        print("[bench]   forward %d steps: %.1f s" % (steps, t1 - t0), file=sys.stderr, flush=True)
         obs, grads = twa.adjoint(pump, B, dt, steps, seed=0, precision="fp32", ckpt_every=ck, objectives=("g2",),
                                  norm_tol=-1)
         torch.cuda.synchronize()
         t2 = time.time()
+        print("[bench]   adjoint for g2: %.1f s" % (t2 - t1), file=sys.stderr, flush=True)
         twa.adjoint(pump, B, dt, steps, seed=0, precision="fp32", ckpt_every=ck, norm_tol=-1)
         torch.cuda.synchronize()
         t3 = time.time()
+        print("[bench]   adjoint for both objectives: %.1f s" % (t3 - t2), file=sys.stderr, flush=True)
         fwd.append(t1 - t0)
         adj.append(t2 - t1)
         adj2.append(t3 - t2)
@@ -155,6 +158,27 @@ def adjoint_cost(twa, steps=2048, reps=1):
                        "ckpt_every": ck, "tile_config": r.obs["tile_config"], "integrator": "heun"},
             "forward_ms_per_step": 1e3 * f / steps, "adjoint_ms_per_step": 1e3 * a / steps,
             "max_norm_dev": obs["max_norm_dev"], "gradients": grads}
+
+
+def gradient_check(twa, steps, prec, hs):
+    """dg2/dw on the adjoint workload's path (N = 2000, 2048 trajectories,
+    fixed noise) by the forward-mode tangent and by central differences of
+    the forward run at w +- h (pumps rebuilt), for each h."""
+    N, B, w, alpha, dt = 2000, 2048, 2.0, 1.0, 1e-4
+    pump = twa.build_pump(N, w, alpha)
+    _, tg = twa.tangent_w(pump, B, dt, steps, seed=0, precision=prec, norm_tol=-1)
+    print("[bench]   forward-mode dg2/dw: %.6g" % tg["d_g2_dw"], file=sys.stderr, flush=True)
+    fd = {}
+    for h in hs:
+        g2 = []
+        for sgn in (1, -1):
+            ph = twa.build_pump(N, w + sgn * h, alpha)
+            g2.append(twa.run(ph, B, dt, steps, seed=0, precision=prec, norm_tol=-1).obs["g2"])
+            ph.close()
+        fd["%g" % h] = (g2[0] - g2[1]) / (2 * h)
+        print("[bench]   central difference (h = %g): %.6g" % (h, fd["%g" % h]), file=sys.stderr, flush=True)
+    return {"steps": steps, "precision": prec, "d_g2_dw_forward_mode": tg["d_g2_dw"],
+            "d_g2_dw_central_difference_by_h": fd}
 
 
 def scan_points(n_points=96, seed=0):
@@ -337,9 +361,11 @@ def two_time_cost(twa, N=1000, w=1.0, alpha=1.0, B=4096, dt=1e-4, T=4000, lags=5
     stride = max(1, (T - burn) // lags)
     twa.run(pump, B, dt, 64, seed=0, precision=prec, norm_tol=-1)
     plain = twa.run(pump, B, dt, T, seed=0, precision=prec, burnin=burn, norm_tol=-1).obs["kernel_ms"]
+    print("[bench]   plain run %d steps: %.1f s of device time" % (T, plain / 1e3), file=sys.stderr, flush=True)
     twa.run(pump, B, dt, 64, seed=0, precision=prec, burnin=32, n_lags=16, lag_stride=2, norm_tol=-1)
     r = twa.run(pump, B, dt, T, seed=0, precision=prec, burnin=burn, n_lags=lags, lag_stride=stride, norm_tol=-1)
     lagged = r.obs["kernel_ms"]
+    print("[bench]   run with %d lags: %.1f s of device time" % (lags, lagged / 1e3), file=sys.stderr, flush=True)
     per_step = plain / T
     window = (lagged - plain) / (T - burn) + per_step
     return {"config": {"N": N, "w": w, "alpha": alpha, "n_traj": B, "dt": dt, "n_steps": T, "burnin": burn,
@@ -466,6 +492,15 @@ def main():
                     help="also time the Newton threshold searches against bisection")
     ap.add_argument("--two-time", action="store_true",
                     help="also time the two-time correlation window (N = 1000, 4096 trajectories, FP32)")
+    ap.add_argument("--two-time-steps", type=int, default=4000,
+                    help="with --two-time: integration steps (window over the last half)")
+    ap.add_argument("--two-time-lags", type=int, default=500, help="with --two-time: number of lags")
+    ap.add_argument("--adjoint-steps", type=int, default=2048,
+                    help="integration steps of the adjoint cost line (N = 2000, 2048 trajectories)")
+    ap.add_argument("--adjoint", action="store_true", help="the adjoint cost line also with --headline-only")
+    ap.add_argument("--gradient-check", default="", choices=["", "fp32", "fp64"],
+                    help="dg2/dw on the adjoint workload by forward mode and by central differences at several h "
+                         "(--adjoint-steps steps) in this precision")
     ap.add_argument("--batch-scan", type=int, default=0,
                     help="also time the 96-point scan for this many steps")
     ap.add_argument("--batch-singles", action="store_true",
@@ -499,7 +534,8 @@ def main():
         toeplitz_only(twa, N, w, alpha, B, dt)
         return
     if args.headline_only:
-        args.no_cpu_baseline = args.no_adjoint = args.no_toeplitz = args.no_heun = True
+        args.no_cpu_baseline = args.no_toeplitz = args.no_heun = True
+        args.no_adjoint = not args.adjoint
         args.no_precision = args.no_linewidth = True
     workload = "n1e4"
     print("[bench] building pump N=%d alpha=%g w=%.4f" % (N, alpha, w), file=sys.stderr, flush=True)
@@ -583,7 +619,8 @@ def main():
         line["threshold"] = threshold_vs_scan(twa)
     if args.two_time:
         print("[bench] two-time correlation window (N=1000, FP32)", file=sys.stderr, flush=True)
-        line["two_time"] = two_time_cost(twa)
+        line["two_time"] = two_time_cost(twa, T=args.two_time_steps, lags=args.two_time_lags)
+        print("[bench]   " + json.dumps(line["two_time"]), file=sys.stderr, flush=True)
     if args.batch_scan > 0:
         print("[bench] batched scan, 96 points, %d steps" % args.batch_scan, file=sys.stderr, flush=True)
         line["batch_scan"] = batch_scan(twa, args.batch_scan, singles=args.batch_singles)
@@ -592,7 +629,13 @@ def main():
         line["batch_singles"] = batch_singles(twa, args.batch_singles_only)
     if not args.no_adjoint:
         print("[bench] adjoint cost ratio (N=2000, FP32)", file=sys.stderr, flush=True)
-        line["adjoint"] = adjoint_cost(twa)
+        line["adjoint"] = adjoint_cost(twa, steps=args.adjoint_steps)
+        print("[bench]   " + json.dumps(line["adjoint"]), file=sys.stderr, flush=True)
+    if args.gradient_check:
+        print("[bench] gradient check (N=2000, %s, %d steps)" % (args.gradient_check, args.adjoint_steps),
+              file=sys.stderr, flush=True)
+        hs = (1e-3, 1e-4, 1e-5, 1e-6) if args.gradient_check == "fp32" else (1e-5, 1e-6, 1e-7, 1e-8)
+        line["gradient_check"] = gradient_check(twa, args.adjoint_steps, args.gradient_check, hs)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         line["cpu_baseline"], opump_ = cpu_baseline(N, w, alpha, dt, integ)
