@@ -23,9 +23,17 @@
  *     caller; pointers documented as "device" are HIP device memory owned by
  *     the caller.  Library-owned objects (twa_pump) are released with their
  *     free function.
- *   - `stream` arguments are hipStream_t passed as void* (NULL = the null
- *     stream).  Every compute entry point is stream-ordered on that stream
- *     and returns after its results are on the host unless stated otherwise.
+ *   - `stream` arguments are hipStream_t passed as void*.  Every compute
+ *     entry point is stream-ordered on that stream and returns after its
+ *     results are on the host unless stated otherwise; with NULL it runs on a
+ *     non-blocking stream of its own (twa_run_noalloc: on the null stream).
+ *   - Host threads: entry points may be called from several threads at
+ *     once.  Each call owns its buffers; pump handles are only read by runs
+ *     and may be shared between concurrent calls.  Calls that replay
+ *     hipGraphs capture them in thread-local mode on their own stream, and no
+ *     call issues work on the null stream or waits for the whole device
+ *     (twa_run_noalloc given NULL aside), so one thread's capture never sees
+ *     another thread's allocations, clears, copies or pump builds.
  *   - All arithmetic of the time stepping runs in the library's HIP kernels
  *     for gfx950.  There is no CPU fallback: without a usable GPU every
  *     compute entry point returns TWA_EHIP.

@@ -184,7 +184,7 @@ int src_init(const Geometry& g, const void* part, const double (*cf)[5], double 
 
 // dF/dalpha from F X + X F = dW/dalpha, solved in the eigenbasis of W:
 // X = V [(V^T dW V)_ij / (r_i + r_j)] V^T, r = sqrt(lambda+) (FP64, one-time)
-int dfactor_dalpha(const twa_pump* p, double* Wa, double* Fa) {
+int dfactor_dalpha(const twa_pump* p, double* Wa, double* Fa, hipStream_t st) {
     const int64_t N = p->N;
     const size_t bytes = (size_t)N * N * sizeof(double);
     double *T = nullptr, *U = nullptr, *r = nullptr;
@@ -201,13 +201,14 @@ int dfactor_dalpha(const twa_pump* p, double* Wa, double* Fa) {
         rc = TWA_ENOMEM;
         goto done;
     }
-    if (rocblas_create_handle(&h) != rocblas_status_success) {
+    if (rocblas_create_handle(&h) != rocblas_status_success || rocblas_set_stream(h, st) != rocblas_status_success) {
         set_error("twa_adjoint: rocblas_create_handle failed");
         rc = TWA_EHIP;
         goto done;
     }
-    hipLaunchKernelGGL(dw_dalpha_kernel, dim3(nblk(N * N, 256)), dim3(256), 0, 0, p->W, N, Wa);
-    if (hipMemcpy(r, rr.data(), N * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+    hipLaunchKernelGGL(dw_dalpha_kernel, dim3(nblk(N * N, 256)), dim3(256), 0, st, p->W, N, Wa);
+    if (hipMemcpyAsync(r, rr.data(), N * sizeof(double), hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess ||
         rocblas_dgemm(h, rocblas_operation_transpose, rocblas_operation_none, n, n, n, &one, p->V, n, Wa, n, &zero, U,
                       n) != rocblas_status_success ||
         rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, n, n, n, &one, U, n, p->V, n, &zero, T, n) !=
@@ -216,7 +217,7 @@ int dfactor_dalpha(const twa_pump* p, double* Wa, double* Fa) {
         rc = TWA_EHIP;
         goto done;
     }
-    hipLaunchKernelGGL(sylvester_scale_kernel, dim3(nblk(N * N, 256)), dim3(256), 0, 0, T, r, N);
+    hipLaunchKernelGGL(sylvester_scale_kernel, dim3(nblk(N * N, 256)), dim3(256), 0, st, T, r, N);
     if (rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, n, n, n, &one, p->V, n, T, n, &zero, U, n) !=
             rocblas_status_success ||
         rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_transpose, n, n, n, &one, U, n, p->V, n, &zero, Fa,
@@ -225,8 +226,8 @@ int dfactor_dalpha(const twa_pump* p, double* Wa, double* Fa) {
         rc = TWA_EHIP;
         goto done;
     }
-    hipLaunchKernelGGL(symmetrize_kernel2, dim3(nblk(N * N, 256)), dim3(256), 0, 0, N, Fa);
-    if (hipDeviceSynchronize() != hipSuccess) {
+    hipLaunchKernelGGL(symmetrize_kernel2, dim3(nblk(N * N, 256)), dim3(256), 0, st, N, Fa);
+    if (hipStreamSynchronize(st) != hipSuccess) {
         set_error("twa_adjoint: dF/dalpha kernels failed");
         rc = TWA_EHIP;
     }
@@ -268,14 +269,14 @@ struct SegStore {
     }
 };
 
-int dalloc0(void** p, size_t bytes) {
+int dalloc0(void** p, size_t bytes, hipStream_t st) {
     if (hipMalloc(p, bytes ? bytes : 16) != hipSuccess) {
         *p = nullptr;
         set_error("twa_adjoint: device allocation of " + std::to_string(bytes) + " bytes failed");
         return TWA_ENOMEM;
     }
-    if (hipMemset(*p, 0, bytes ? bytes : 16) != hipSuccess) {
-        set_error("twa_adjoint: hipMemset failed");
+    if (hipMemsetAsync(*p, 0, bytes ? bytes : 16, st) != hipSuccess) {
+        set_error("twa_adjoint: hipMemsetAsync failed");
         return TWA_EHIP;
     }
     return TWA_OK;
@@ -304,7 +305,7 @@ int adjoint_impl(const twa_params* p, int64_t n_traj, double dt, int64_t n_steps
     hipStream_t st = (hipStream_t)p->stream;
     hipStream_t own = nullptr;
     if (!st) {
-        if (hipStreamCreate(&own) != hipSuccess) {
+        if (hipStreamCreateWithFlags(&own, hipStreamNonBlocking) != hipSuccess) {
             set_error("twa_adjoint: hipStreamCreate failed (no usable GPU?)");
             return TWA_EHIP;
         }
@@ -364,31 +365,31 @@ int adjoint_impl(const twa_params* p, int64_t n_traj, double dt, int64_t n_steps
             goto cleanup;
         }
     }
-    TWA_TRY(alloc_buffers(g, false, 0, J, b));
-    TWA_TRY(dalloc0(&m.s, plane * 3 * (K + 1)));
-    TWA_TRY(dalloc0(&m.d, plane * 3 * K));
-    TWA_TRY(dalloc0(&m.y1, plane * 2 * K));
-    TWA_TRY(dalloc0(&m.y2, plane * 2 * K));
-    TWA_TRY(dalloc0(&m.q, plane * 2 * K));
-    TWA_TRY(dalloc0(&m.ya1, plane * 2 * K));
-    TWA_TRY(dalloc0(&m.ya2, plane * 2 * K));
-    TWA_TRY(dalloc0(&m.partS, partsz * (K + 1)));
-    TWA_TRY(dalloc0(&m.partP, partsz * K));
-    TWA_TRY(dalloc0(&m.g, (size_t)2 * g.Bp * se * K));
-    TWA_TRY(dalloc0(&m.ckpt, plane * 3 * nseg));
-    TWA_TRY(dalloc0(&m.ckpt_part, partsz * nseg));
-    TWA_TRY(dalloc0(&m.Aa, (size_t)g.P * 2 * g.P * ge));
-    TWA_TRY(dalloc0(&m.lam, plane * 6));
-    TWA_TRY(dalloc0(&m.M1, plane * 6));
-    TWA_TRY(dalloc0(&m.Rb, plane * 6));
-    TWA_TRY(dalloc0(&m.nu2, (size_t)2 * g.C2 * g.P * ge));
-    TWA_TRY(dalloc0(&m.nu1, (size_t)2 * g.C2 * g.P * ge));
-    TWA_TRY(dalloc0(&m.nu2p, partsz * 2));
-    TWA_TRY(dalloc0(&m.nu1p, partsz * 2));
-    TWA_TRY(dalloc0((void**)&m.gacc, (size_t)4 * g.nmt * g.Bp * sizeof(double)));
+    TWA_TRY(alloc_buffers(g, false, 0, J, b, st));
+    TWA_TRY(dalloc0(&m.s, plane * 3 * (K + 1), st));
+    TWA_TRY(dalloc0(&m.d, plane * 3 * K, st));
+    TWA_TRY(dalloc0(&m.y1, plane * 2 * K, st));
+    TWA_TRY(dalloc0(&m.y2, plane * 2 * K, st));
+    TWA_TRY(dalloc0(&m.q, plane * 2 * K, st));
+    TWA_TRY(dalloc0(&m.ya1, plane * 2 * K, st));
+    TWA_TRY(dalloc0(&m.ya2, plane * 2 * K, st));
+    TWA_TRY(dalloc0(&m.partS, partsz * (K + 1), st));
+    TWA_TRY(dalloc0(&m.partP, partsz * K, st));
+    TWA_TRY(dalloc0(&m.g, (size_t)2 * g.Bp * se * K, st));
+    TWA_TRY(dalloc0(&m.ckpt, plane * 3 * nseg, st));
+    TWA_TRY(dalloc0(&m.ckpt_part, partsz * nseg, st));
+    TWA_TRY(dalloc0(&m.Aa, (size_t)g.P * 2 * g.P * ge, st));
+    TWA_TRY(dalloc0(&m.lam, plane * 6, st));
+    TWA_TRY(dalloc0(&m.M1, plane * 6, st));
+    TWA_TRY(dalloc0(&m.Rb, plane * 6, st));
+    TWA_TRY(dalloc0(&m.nu2, (size_t)2 * g.C2 * g.P * ge, st));
+    TWA_TRY(dalloc0(&m.nu1, (size_t)2 * g.C2 * g.P * ge, st));
+    TWA_TRY(dalloc0(&m.nu2p, partsz * 2, st));
+    TWA_TRY(dalloc0(&m.nu1p, partsz * 2, st));
+    TWA_TRY(dalloc0((void**)&m.gacc, (size_t)4 * g.nmt * g.Bp * sizeof(double), st));
     TWA_HTRY(hipMalloc(&Wa, (size_t)N * N * sizeof(double)));
     TWA_HTRY(hipMalloc(&Fa, (size_t)N * N * sizeof(double)));
-    TWA_TRY(dfactor_dalpha(pump, Wa, Fa));
+    TWA_TRY(dfactor_dalpha(pump, Wa, Fa, st));
     TWA_TRY(launch_build_A(g, pump->W, pump->F, dt, b.A, st));
     TWA_TRY(launch_build_A(g, Wa, Fa, dt, m.Aa, st));
     TWA_TRY(launch_init_state(g, b, c, nullptr, st));

@@ -248,7 +248,7 @@ int build_bucket(const BatchSpec& sp, const std::vector<int>& idx, int cfg, Buck
         g = make_geometry(o->precision, cfg, pt.N, o->n_traj);
         g.integrator = o->integrator;
         EnsembleBuffers& b = bk.bs[(size_t)q];
-        if ((rc = alloc_buffers(g, tangents, sp.L, bk.J, b))) return rc;
+        if ((rc = alloc_buffers(g, tangents, sp.L, bk.J, b, st))) return rc;
         hipFree(b.step);
         b.step = bk.step;   // one step counter for the bucket
         StepConsts& c = bk.cs[(size_t)q];
@@ -290,11 +290,13 @@ int build_bucket(const BatchSpec& sp, const std::vector<int>& idx, int cfg, Buck
     }
     bk.nblocks_noise = bstart[(size_t)np];
     TWA_HIP_CHECK(hipMalloc(&bk.d_pd, pd.size() * sizeof(PointDesc)));
-    TWA_HIP_CHECK(hipMemcpy(bk.d_pd, pd.data(), pd.size() * sizeof(PointDesc), hipMemcpyHostToDevice));
+    TWA_HIP_CHECK(hipMemcpyAsync(bk.d_pd, pd.data(), pd.size() * sizeof(PointDesc), hipMemcpyHostToDevice, st));
     TWA_HIP_CHECK(hipMalloc(&bk.d_bstart, bstart.size() * sizeof(int)));
-    TWA_HIP_CHECK(hipMemcpy(bk.d_bstart, bstart.data(), bstart.size() * sizeof(int), hipMemcpyHostToDevice));
+    TWA_HIP_CHECK(hipMemcpyAsync(bk.d_bstart, bstart.data(), bstart.size() * sizeof(int), hipMemcpyHostToDevice,
+                                 st));
+    TWA_HIP_CHECK(hipStreamSynchronize(st));   // the host arrays end with this function
     TWA_HIP_CHECK(hipMemsetAsync(bk.step, 0, sizeof(int64_t), st));
-    if ((rc = grouped_prepare(bk.gs, bk.bs, bk.cs, bk.step, tangents, bk.plan))) return rc;
+    if ((rc = grouped_prepare(bk.gs, bk.bs, bk.cs, bk.step, tangents, bk.plan, st))) return rc;
     if (sp.L > 0 && sp.burnin == 0) {
         // the origin is the initial state: seed the response copies and observe it
         for (int q = 0; q < np; ++q)
@@ -554,7 +556,7 @@ int run_batch(const twa_point* pts, int np, const twa_batch_opts* o, twa_observa
     hipStream_t st = (hipStream_t)o->stream;
     hipStream_t own = nullptr;
     if (!st) {
-        if (hipStreamCreate(&own) != hipSuccess) {
+        if (hipStreamCreateWithFlags(&own, hipStreamNonBlocking) != hipSuccess) {
             set_error("twa_run_batch: hipStreamCreate failed (no usable GPU?)");
             return TWA_EHIP;
         }
@@ -605,7 +607,7 @@ int run_batch(const twa_point* pts, int np, const twa_batch_opts* o, twa_observa
             }
         for (size_t b = 0; b < bks.size(); ++b) {
             if (bks.size() > 1) {
-                if (hipStreamCreate(&branch[b]) != hipSuccess) {
+                if (hipStreamCreateWithFlags(&branch[b], hipStreamNonBlocking) != hipSuccess) {
                     set_error("twa_run_batch: hipStreamCreate failed");
                     rc = TWA_EHIP;
                     goto cleanup;

@@ -160,7 +160,8 @@ struct GroupedPlan {
     int64_t* step = nullptr;
 };
 int grouped_prepare(const std::vector<Geometry>& gs, const std::vector<EnsembleBuffers>& bs,
-                    const std::vector<StepConsts>& cs, int64_t* step, bool tangents, GroupedPlan& pl);
+                    const std::vector<StepConsts>& cs, int64_t* step, bool tangents, GroupedPlan& pl,
+                    hipStream_t st);
 // per-precision launchers, instantiated one precision per translation unit
 // (twa_step_<precision>.hip); launch_gemm, launch_gemm_call, grouped_prepare
 // and grouped_launch dispatch to them
@@ -171,7 +172,8 @@ template <int PREC>
 int launch_call_p(const Geometry& g, const GemmCall& c, hipStream_t st);
 template <int PREC>
 int grouped_prepare_p(const std::vector<Geometry>& gs, const std::vector<EnsembleBuffers>& bs,
-                      const std::vector<StepConsts>& cs, int64_t* step, bool tangents, GroupedPlan& pl);
+                      const std::vector<StepConsts>& cs, int64_t* step, bool tangents, GroupedPlan& pl,
+                      hipStream_t st);
 template <int PREC>
 int grouped_launch_p(const GroupedPlan& pl, int stage, int cur, int variant, hipStream_t st);
 int grouped_launch(const GroupedPlan& pl, int stage, int cur, int variant, hipStream_t st);
@@ -206,7 +208,7 @@ int launch_small_run(const Geometry& g, const EnsembleBuffers& b, const StepCons
 // estimator of correlated emission; the geometry pads trajectories to a
 // multiple of the column tile
 int decay_geometry_ok(const Geometry& g);
-int alloc_decay_buffers(const Geometry& g, EnsembleBuffers& b);
+int alloc_decay_buffers(const Geometry& g, EnsembleBuffers& b, hipStream_t st);
 int launch_decay_ops(const Geometry& g, const double* G, const EnsembleBuffers& b, hipStream_t st);
 int launch_decay_observe(const Geometry& g, const EnsembleBuffers& b, int cur, hipStream_t st);
 
@@ -215,7 +217,7 @@ int launch_decay_observe(const Geometry& g, const EnsembleBuffers& b, int cur, h
 int toeplitz_embedding_log2(int64_t N);
 double toeplitz_spectrum_max(int64_t N, double w, double alpha);
 int64_t toeplitz_max_n(int precision);
-int toeplitz_tables(const Geometry& g, double w, double alpha, double dt, void** tw, void** spec);
+int toeplitz_tables(const Geometry& g, double w, double alpha, double dt, void** tw, void** spec, hipStream_t st);
 int launch_toeplitz_run(const Geometry& g, const EnsembleBuffers& b, const StepConsts& c, const void* tw,
                         const void* spec, int64_t n_steps, int cur, hipStream_t st);
 

@@ -39,7 +39,28 @@ __global__ void symmetrize_kernel(int64_t N, double* F) {
     F[j * N + i] = v;
 }
 
-static int factorise(twa_pump* p) {
+// The builders work on a stream of their own, non-blocking, and synchronise
+// only that stream: they never wait on, or make null-stream work wait on,
+// streams that other threads may be capturing into graphs.
+struct BuildStream {
+    hipStream_t s = nullptr;
+    BuildStream() = default;
+    BuildStream(const BuildStream&) = delete;
+    BuildStream& operator=(const BuildStream&) = delete;
+    ~BuildStream() {
+        if (s) hipStreamDestroy(s);
+    }
+    int create(const char* who) {
+        if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+            s = nullptr;
+            set_error(std::string(who) + ": hipStreamCreateWithFlags failed (no usable GPU?)");
+            return TWA_EHIP;
+        }
+        return TWA_OK;
+    }
+};
+
+static int factorise(twa_pump* p, hipStream_t st) {
     const int64_t N = p->N;
     if (N > 46340) {
         set_error("N too large for a dense FP64 factorisation on one device");
@@ -62,11 +83,11 @@ static int factorise(twa_pump* p) {
         fail(TWA_ENOMEM, "device allocation for the pump factorisation failed");
         goto done;
     }
-    if (rocblas_create_handle(&h) != rocblas_status_success) {
+    if (rocblas_create_handle(&h) != rocblas_status_success || rocblas_set_stream(h, st) != rocblas_status_success) {
         fail(TWA_EHIP, "rocblas_create_handle failed");
         goto done;
     }
-    if (hipMemcpy(p->V, p->W, bytes, hipMemcpyDeviceToDevice) != hipSuccess) {
+    if (hipMemcpyAsync(p->V, p->W, bytes, hipMemcpyDeviceToDevice, st) != hipSuccess) {
         fail(TWA_EHIP, "hipMemcpy failed");
         goto done;
     }
@@ -78,8 +99,9 @@ static int factorise(twa_pump* p) {
     }
     {
         rocblas_int hinfo = 0;
-        if (hipMemcpy(&hinfo, info, sizeof(hinfo), hipMemcpyDeviceToHost) != hipSuccess ||
-            hipMemcpy(lam.data(), D, N * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) {
+        if (hipMemcpyAsync(&hinfo, info, sizeof(hinfo), hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipMemcpyAsync(lam.data(), D, N * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess) {
             fail(TWA_EHIP, "hipMemcpy failed");
             goto done;
         }
@@ -105,13 +127,13 @@ static int factorise(twa_pump* p) {
         goto done;
     }
     for (int64_t j = 0; j < N; ++j) p->lam[j] = lam[(size_t)j];
-    if (hipMemcpy(r, rr.data(), N * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+    if (hipMemcpyAsync(r, rr.data(), N * sizeof(double), hipMemcpyHostToDevice, st) != hipSuccess) {
         fail(TWA_EHIP, "hipMemcpy failed");
         goto done;
     }
     {
         const int64_t n2 = N * N;
-        hipLaunchKernelGGL(scale_columns_kernel, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, 0, N, p->V, r, Vs);
+        hipLaunchKernelGGL(scale_columns_kernel, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, st, N, p->V, r, Vs);
         const double one = 1.0, zero = 0.0;
         // column-major F = (V diag(sqrt(lambda+))) V^T
         if (rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_transpose, (rocblas_int)N, (rocblas_int)N,
@@ -120,13 +142,14 @@ static int factorise(twa_pump* p) {
             fail(TWA_EHIP, "rocblas_dgemm failed");
             goto done;
         }
-        hipLaunchKernelGGL(symmetrize_kernel, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, 0, N, p->F);
-        if (hipDeviceSynchronize() != hipSuccess) {
+        hipLaunchKernelGGL(symmetrize_kernel, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, st, N, p->F);
+        if (hipStreamSynchronize(st) != hipSuccess) {
             fail(TWA_EHIP, "pump factorisation kernels failed");
             goto done;
         }
     }
 done:
+    hipStreamSynchronize(st);
     if (h) rocblas_destroy_handle(h);
     hipFree(D);
     hipFree(E);
@@ -198,11 +221,17 @@ int pump_scaled(const twa_pump* b, double w, twa_pump** out) {
     }
     for (int64_t j = 0; j < N; ++j) p->lam[j] = f * b->lam[j];
     const unsigned nb = (unsigned)((n2 + 255) / 256);
-    hipLaunchKernelGGL(scale_kernel, dim3(nb), dim3(256), 0, 0, n2, b->W, f, p->W);
-    hipLaunchKernelGGL(scale_kernel, dim3(nb), dim3(256), 0, 0, n2, b->F, std::sqrt(f), p->F);
+    BuildStream bs;
+    if (bs.create("pump_scaled")) {
+        pump_release(p);
+        return TWA_EHIP;
+    }
+    hipLaunchKernelGGL(scale_kernel, dim3(nb), dim3(256), 0, bs.s, n2, b->W, f, p->W);
+    hipLaunchKernelGGL(scale_kernel, dim3(nb), dim3(256), 0, bs.s, n2, b->F, std::sqrt(f), p->F);
     if (hipGetLastError() != hipSuccess ||
-        hipMemcpy(p->V, b->V, bytes, hipMemcpyDeviceToDevice) != hipSuccess ||
-        hipDeviceSynchronize() != hipSuccess) {
+        hipMemcpyAsync(p->V, b->V, bytes, hipMemcpyDeviceToDevice, bs.s) != hipSuccess ||
+        hipStreamSynchronize(bs.s) != hipSuccess) {
+        hipStreamSynchronize(bs.s);
         pump_release(p);
         set_error("pump_scaled: scaling failed");
         return TWA_EHIP;
@@ -233,13 +262,19 @@ TWA_API int twa_build_pump(int64_t N, double w, double alpha, twa_pump** out) {
         return TWA_ENOMEM;
     }
     const int64_t n2 = N * N;
-    hipLaunchKernelGGL(pump_matrix_kernel, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, 0, N, w, alpha, p->W);
+    BuildStream bs;
+    if (bs.create("twa_build_pump")) {
+        pump_release(p);
+        return TWA_EHIP;
+    }
+    hipLaunchKernelGGL(pump_matrix_kernel, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, bs.s, N, w, alpha, p->W);
     if (hipGetLastError() != hipSuccess) {
+        hipStreamSynchronize(bs.s);
         pump_release(p);
         set_error("twa_build_pump: kernel launch failed");
         return TWA_EHIP;
     }
-    int rc = factorise(p);
+    int rc = factorise(p, bs.s);
     if (rc) {
         pump_release(p);
         return rc;
@@ -273,12 +308,18 @@ TWA_API int twa_build_pump_dense(int64_t N, const double* W_host, twa_pump** out
         set_error("twa_build_pump_dense: device allocation failed");
         return TWA_ENOMEM;
     }
-    if (hipMemcpy(p->W, W_host, (size_t)N * N * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+    BuildStream bs;
+    if (bs.create("twa_build_pump_dense")) {
+        pump_release(p);
+        return TWA_EHIP;
+    }
+    if (hipMemcpyAsync(p->W, W_host, (size_t)N * N * sizeof(double), hipMemcpyHostToDevice, bs.s) != hipSuccess) {
+        hipStreamSynchronize(bs.s);
         pump_release(p);
         set_error("twa_build_pump_dense: hipMemcpy failed");
         return TWA_EHIP;
     }
-    int rc = factorise(p);
+    int rc = factorise(p, bs.s);
     if (rc) {
         pump_release(p);
         return rc;
@@ -310,6 +351,8 @@ TWA_API int twa_build_model_dense(int64_t N, const double* W_host, const double*
     const int64_t n2 = N * N;
     const unsigned nb = (unsigned)((n2 + 255) / 256);
     int rc;
+    BuildStream bs;
+    if ((rc = bs.create("twa_build_model_dense"))) return rc;
     // the decay matrix itself must be PSD (a physical Lindbladian)
     {
         twa_pump* q = new twa_pump();
@@ -320,12 +363,13 @@ TWA_API int twa_build_model_dense(int64_t N, const double* W_host, const double*
             set_error("twa_build_model_dense: device allocation failed");
             return TWA_ENOMEM;
         }
-        if (hipMemcpy(q->W, G_host, bytes, hipMemcpyHostToDevice) != hipSuccess) {
+        if (hipMemcpyAsync(q->W, G_host, bytes, hipMemcpyHostToDevice, bs.s) != hipSuccess) {
+            hipStreamSynchronize(bs.s);
             pump_release(q);
             set_error("twa_build_model_dense: hipMemcpy failed");
             return TWA_EHIP;
         }
-        rc = factorise(q);
+        rc = factorise(q, bs.s);
         pump_release(q);
         if (rc == TWA_ENOTPSD) set_error("twa_build_model_dense: decay matrix is not positive semidefinite");
         if (rc) return rc;
@@ -343,31 +387,34 @@ TWA_API int twa_build_model_dense(int64_t N, const double* W_host, const double*
         set_error("twa_build_model_dense: device allocation failed");
         return TWA_ENOMEM;
     }
-    if (hipMemcpy(Wd, W_host, bytes, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(p->G, G_host, bytes, hipMemcpyHostToDevice) != hipSuccess) {
+    if (hipMemcpyAsync(Wd, W_host, bytes, hipMemcpyHostToDevice, bs.s) != hipSuccess ||
+        hipMemcpyAsync(p->G, G_host, bytes, hipMemcpyHostToDevice, bs.s) != hipSuccess) {
+        hipStreamSynchronize(bs.s);
         hipFree(Wd);
         pump_release(p);
         set_error("twa_build_model_dense: hipMemcpy failed");
         return TWA_EHIP;
     }
     // noise factor of the summed noise: sqrt(W + G); then the drift matrix W - G
-    hipLaunchKernelGGL(axpy_kernel, dim3(nb), dim3(256), 0, 0, n2, Wd, 1.0, p->G, p->W);
-    rc = hipGetLastError() == hipSuccess ? factorise(p) : TWA_EHIP;
+    hipLaunchKernelGGL(axpy_kernel, dim3(nb), dim3(256), 0, bs.s, n2, Wd, 1.0, p->G, p->W);
+    rc = hipGetLastError() == hipSuccess ? factorise(p, bs.s) : TWA_EHIP;
     if (rc == TWA_OK) {
-        hipLaunchKernelGGL(axpy_kernel, dim3(nb), dim3(256), 0, 0, n2, Wd, -1.0, p->G, p->W);
-        if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+        hipLaunchKernelGGL(axpy_kernel, dim3(nb), dim3(256), 0, bs.s, n2, Wd, -1.0, p->G, p->W);
+        if (hipGetLastError() != hipSuccess || hipStreamSynchronize(bs.s) != hipSuccess) {
             set_error("twa_build_model_dense: kernel failed");
             rc = TWA_EHIP;
         }
     } else if (rc == TWA_EHIP) {
         set_error("twa_build_model_dense: factorisation of W + G failed");
     }
+    hipStreamSynchronize(bs.s);
     hipFree(Wd);
     if (rc == TWA_OK && Om_host) {
         if (hipMalloc(&p->Om, bytes) != hipSuccess) {
             set_error("twa_build_model_dense: device allocation failed");
             rc = TWA_ENOMEM;
-        } else if (hipMemcpy(p->Om, Om_host, bytes, hipMemcpyHostToDevice) != hipSuccess) {
+        } else if (hipMemcpyAsync(p->Om, Om_host, bytes, hipMemcpyHostToDevice, bs.s) != hipSuccess ||
+                   hipStreamSynchronize(bs.s) != hipSuccess) {
             set_error("twa_build_model_dense: hipMemcpy failed");
             rc = TWA_EHIP;
         }
@@ -422,7 +469,11 @@ TWA_API int twa_pump_copy_matrix(const twa_pump* p, int which, double* out_host)
         twa::set_error("twa_pump_copy_matrix: the handle holds no dense matrices (Toeplitz handle)");
         return TWA_EINVAL;
     }
-    if (hipMemcpy(out_host, src, (size_t)p->N * p->N * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) {
+    twa::BuildStream bs;
+    if (bs.create("twa_pump_copy_matrix")) return TWA_EHIP;
+    if (hipMemcpyAsync(out_host, src, (size_t)p->N * p->N * sizeof(double), hipMemcpyDeviceToHost, bs.s) !=
+            hipSuccess ||
+        hipStreamSynchronize(bs.s) != hipSuccess) {
         twa::set_error("twa_pump_copy_matrix: hipMemcpy failed");
         return TWA_EHIP;
     }

@@ -56,7 +56,7 @@ inline double effective_norm_tol(double t) { return t == 0 ? 1e-2 : t; }
 int run_status(const char* who, bool nan, double max_norm_dev, double norm_tol);
 
 void free_buffers(EnsembleBuffers& b);
-int alloc_buffers(const Geometry& g, bool tangents, int64_t L, int J, EnsembleBuffers& b);
+int alloc_buffers(const Geometry& g, bool tangents, int64_t L, int J, EnsembleBuffers& b, hipStream_t st);
 Geometry make_geometry(int precision, int cfg, int64_t N, int64_t B);
 void finalize_moments(const std::vector<double>& traj, int64_t B, twa_observables* o);
 // the same from the jackknife block sums bsum [J][5] of the per-trajectory

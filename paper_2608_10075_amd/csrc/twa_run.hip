@@ -287,26 +287,29 @@ void free_buffers(EnsembleBuffers& b) {
     b = EnsembleBuffers();
 }
 
-static int dalloc(void** p, size_t bytes) {
+// device allocation cleared on the run's stream (never the null stream: a
+// null-stream operation would synchronise with streams that other threads
+// may be capturing into graphs)
+static int dalloc(void** p, size_t bytes, hipStream_t st) {
     if (bytes == 0) bytes = 16;
     if (hipMalloc(p, bytes) != hipSuccess) {
         *p = nullptr;
         set_error("device allocation of " + std::to_string(bytes) + " bytes failed");
         return TWA_ENOMEM;
     }
-    if (hipMemset(*p, 0, bytes) != hipSuccess) {
-        set_error("hipMemset failed");
+    if (hipMemsetAsync(*p, 0, bytes, st) != hipSuccess) {
+        set_error("hipMemsetAsync failed");
         return TWA_EHIP;
     }
     return TWA_OK;
 }
 
-int alloc_buffers(const Geometry& g, bool tangents, int64_t L, int J, EnsembleBuffers& b) {
+int alloc_buffers(const Geometry& g, bool tangents, int64_t L, int J, EnsembleBuffers& b, hipStream_t st) {
     const size_t ge = (size_t)gemm_elt_bytes(g.precision), se = (size_t)state_elt_bytes(g.precision);
     const size_t P = (size_t)g.P, Bp = (size_t)g.Bp, C2 = (size_t)g.C2, nmt = (size_t)g.nmt;
     int rc;
 #define TWA_A(ptr, bytes) \
-    if ((rc = dalloc((void**)&(ptr), (bytes))) != TWA_OK) return rc;
+    if ((rc = dalloc((void**)&(ptr), (bytes), st)) != TWA_OK) return rc;
     const size_t spl = (size_t)operand_split(g.precision);   // split form: hi, lo, hi blocks
     const size_t ck = g.coh ? 1 : 0;                          // coherent exchange: one more K block
     TWA_A(b.A, P * (2 + ck) * P * ge * spl)
@@ -345,13 +348,14 @@ int alloc_buffers(const Geometry& g, bool tangents, int64_t L, int J, EnsembleBu
     return TWA_OK;
 }
 
-int alloc_decay_buffers(const Geometry& g, EnsembleBuffers& b) {
+int alloc_decay_buffers(const Geometry& g, EnsembleBuffers& b, hipStream_t st) {
     const size_t ge = (size_t)gemm_elt_bytes(g.precision), se = (size_t)state_elt_bytes(g.precision);
     const size_t P = (size_t)g.P, Bp = (size_t)g.Bp;
     int rc;
-    if ((rc = dalloc(&b.AG, P * P * ge)) || (rc = dalloc(&b.AGG, P * P * ge)) || (rc = dalloc(&b.Zop, Bp * P * ge)) ||
-        (rc = dalloc(&b.GX, 2 * Bp * P * se)) || (rc = dalloc(&b.UZ, Bp * P * se)) || (rc = dalloc(&b.dg, P * se)) ||
-        (rc = dalloc((void**)&b.gmom, 18 * Bp * sizeof(double))))
+    if ((rc = dalloc(&b.AG, P * P * ge, st)) || (rc = dalloc(&b.AGG, P * P * ge, st)) ||
+        (rc = dalloc(&b.Zop, Bp * P * ge, st)) || (rc = dalloc(&b.GX, 2 * Bp * P * se, st)) ||
+        (rc = dalloc(&b.UZ, Bp * P * se, st)) || (rc = dalloc(&b.dg, P * se, st)) ||
+        (rc = dalloc((void**)&b.gmom, 18 * Bp * sizeof(double), st)))
         return rc;
     return TWA_OK;
 }

@@ -147,7 +147,7 @@ int run_single(const twa_params* p, int64_t n_traj, double dt, int64_t n_steps, 
     hipStream_t st = (hipStream_t)p->stream;
     hipStream_t own = nullptr;
     if (!st) {
-        if (hipStreamCreate(&own) != hipSuccess) {
+        if (hipStreamCreateWithFlags(&own, hipStreamNonBlocking) != hipSuccess) {
             set_error("twa_run: hipStreamCreate failed (no usable GPU?)");
             return TWA_EHIP;
         }
@@ -198,16 +198,16 @@ int run_single(const twa_params* p, int64_t n_traj, double dt, int64_t n_steps, 
         }                                                                \
     } while (0)
 
-    TWA_TRY(alloc_buffers(g, tangents, L, J, b));
+    TWA_TRY(alloc_buffers(g, tangents, L, J, b, st));
     if (toep)
-        TWA_TRY(toeplitz_tables(g, pump->w, pump->alpha, dt, &toep_tw, &toep_spec));
+        TWA_TRY(toeplitz_tables(g, pump->w, pump->alpha, dt, &toep_tw, &toep_spec, st));
     else if (g.coh)
         TWA_TRY(launch_build_A_coh(g, pump->W, pump->F, pump->Om, dt, b.A, b.A2, st));
     else
         TWA_TRY(launch_build_A(g, pump->W, pump->F, dt, b.A, st));
     if (decay) {
         TWA_TRY(decay_geometry_ok(g));
-        TWA_TRY(alloc_decay_buffers(g, b));
+        TWA_TRY(alloc_decay_buffers(g, b, st));
         TWA_TRY(launch_decay_ops(g, pump->G, b, st));
     }
     if (p->init_state) {

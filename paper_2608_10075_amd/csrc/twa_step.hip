@@ -52,13 +52,14 @@ int launch_gemm_call(const Geometry& g, const GemmCall& c, hipStream_t st) {
 
 
 int grouped_prepare(const std::vector<Geometry>& gs, const std::vector<EnsembleBuffers>& bs,
-                    const std::vector<StepConsts>& cs, int64_t* step, bool tangents, GroupedPlan& pl) {
+                    const std::vector<StepConsts>& cs, int64_t* step, bool tangents, GroupedPlan& pl,
+                    hipStream_t st) {
     if (gs.empty()) return TWA_EINVAL;
     switch (gs[0].precision) {
-        case TWA_PREC_FP32: return grouped_prepare_p<TWA_PREC_FP32>(gs, bs, cs, step, tangents, pl);
-        case TWA_PREC_BF16: return grouped_prepare_p<TWA_PREC_BF16>(gs, bs, cs, step, tangents, pl);
-        case TWA_PREC_FP16: return grouped_prepare_p<TWA_PREC_FP16>(gs, bs, cs, step, tangents, pl);
-        case TWA_PREC_FP64: return grouped_prepare_p<TWA_PREC_FP64>(gs, bs, cs, step, tangents, pl);
+        case TWA_PREC_FP32: return grouped_prepare_p<TWA_PREC_FP32>(gs, bs, cs, step, tangents, pl, st);
+        case TWA_PREC_BF16: return grouped_prepare_p<TWA_PREC_BF16>(gs, bs, cs, step, tangents, pl, st);
+        case TWA_PREC_FP16: return grouped_prepare_p<TWA_PREC_FP16>(gs, bs, cs, step, tangents, pl, st);
+        case TWA_PREC_FP64: return grouped_prepare_p<TWA_PREC_FP64>(gs, bs, cs, step, tangents, pl, st);
     }
     set_error("unknown precision");
     return TWA_EINVAL;

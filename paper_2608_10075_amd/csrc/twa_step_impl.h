@@ -1347,7 +1347,8 @@ inline void xcd_permute(std::vector<int4>& tiles, int grid) {
 
 template <int PREC>
 int grouped_prepare_p(const std::vector<Geometry>& gs, const std::vector<EnsembleBuffers>& bs,
-                             const std::vector<StepConsts>& cs, int64_t* step, bool tangents, GroupedPlan& pl) {
+                             const std::vector<StepConsts>& cs, int64_t* step, bool tangents, GroupedPlan& pl,
+                             hipStream_t st) {
     const int np = (int)gs.size();
     const int cfg = gs[0].cfg;
     const TileCfg& tc = tile_cfg(cfg);
@@ -1364,8 +1365,9 @@ int grouped_prepare_p(const std::vector<Geometry>& gs, const std::vector<Ensembl
                     h[(size_t)p].nnt = (int)(gs[(size_t)p].C2 / tc.nt);
                 }
                 TWA_HIP_CHECK(hipMalloc(&pl.d_args[v][stage - 1][cur], h.size() * sizeof(GemmArgs<PREC>)));
-                TWA_HIP_CHECK(hipMemcpy(pl.d_args[v][stage - 1][cur], h.data(), h.size() * sizeof(GemmArgs<PREC>),
-                                        hipMemcpyHostToDevice));
+                TWA_HIP_CHECK(hipMemcpyAsync(pl.d_args[v][stage - 1][cur], h.data(), h.size() * sizeof(GemmArgs<PREC>),
+                                             hipMemcpyHostToDevice, st));
+                TWA_HIP_CHECK(hipStreamSynchronize(st));   // h ends with this iteration
             }
     int dev = 0, ncu = 0;
     TWA_HIP_CHECK(hipGetDevice(&dev));
@@ -1398,7 +1400,9 @@ int grouped_prepare_p(const std::vector<Geometry>& gs, const std::vector<Ensembl
         const int grid = std::max(1, std::min(ncu * occ, ntl));
         xcd_permute(tiles, grid);
         TWA_HIP_CHECK(hipMalloc((void**)&pl.d_tiles[tl], tiles.size() * sizeof(int4)));
-        TWA_HIP_CHECK(hipMemcpy(pl.d_tiles[tl], tiles.data(), tiles.size() * sizeof(int4), hipMemcpyHostToDevice));
+        TWA_HIP_CHECK(hipMemcpyAsync(pl.d_tiles[tl], tiles.data(), tiles.size() * sizeof(int4), hipMemcpyHostToDevice,
+                                     st));
+        TWA_HIP_CHECK(hipStreamSynchronize(st));   // the host list ends with this iteration
         pl.ntiles[tl] = ntl;
         pl.grid[tl] = grid;
     }

@@ -95,7 +95,7 @@ int run_tangent_w(const twa_params* p, int64_t n_traj, double dt, int64_t n_step
     hipStream_t st = (hipStream_t)p->stream;
     hipStream_t own = nullptr;
     if (!st) {
-        if (hipStreamCreate(&own) != hipSuccess) {
+        if (hipStreamCreateWithFlags(&own, hipStreamNonBlocking) != hipSuccess) {
             set_error("twa_tangent_w: hipStreamCreate failed (no usable GPU?)");
             return TWA_EHIP;
         }
@@ -139,7 +139,7 @@ int run_tangent_w(const twa_params* p, int64_t n_traj, double dt, int64_t n_step
     } while (0)
 
     // the tangent starts at zero: the initial sampling does not depend on w
-    TWA_TRY(alloc_buffers(g, true, 0, J, b));
+    TWA_TRY(alloc_buffers(g, true, 0, J, b, st));
     TWA_HTRY(hipMalloc(&Q, 2 * plane));
     TWA_HTRY(hipMalloc((void**)&dacc, (size_t)5 * g.Bp * sizeof(double)));
     TWA_HTRY(hipMemsetAsync(dacc, 0, (size_t)5 * g.Bp * sizeof(double), st));

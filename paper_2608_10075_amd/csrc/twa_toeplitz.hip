@@ -574,7 +574,7 @@ int64_t toeplitz_max_n(int precision) { return precision == TWA_PREC_FP64 ? 8193
 
 // tables of one run: twiddles w_M^q and the spectral coefficients
 // (lam (-dt / 2M), sqrt(lam+) (-sqrt(dt / M))) in the state precision
-int toeplitz_tables(const Geometry& g, double w, double alpha, double dt, void** tw, void** spec) {
+int toeplitz_tables(const Geometry& g, double w, double alpha, double dt, void** tw, void** spec, hipStream_t st) {
     const int logm = toeplitz_embedding_log2(g.N);
     const int64_t M = int64_t(1) << logm;
     std::vector<std::complex<double>> a((size_t)M);
@@ -602,15 +602,17 @@ int toeplitz_tables(const Geometry& g, double w, double alpha, double dt, void**
         return TWA_ENOMEM;
     }
     if (f64) {
-        if (hipMemcpy(*tw, twd.data(), (size_t)M * es, hipMemcpyHostToDevice) != hipSuccess ||
-            hipMemcpy(*spec, spd.data(), (size_t)M * es, hipMemcpyHostToDevice) != hipSuccess) {
+        if (hipMemcpyAsync(*tw, twd.data(), (size_t)M * es, hipMemcpyHostToDevice, st) != hipSuccess ||
+            hipMemcpyAsync(*spec, spd.data(), (size_t)M * es, hipMemcpyHostToDevice, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess) {
             set_error("Toeplitz path: hipMemcpy failed");
             return TWA_EHIP;
         }
     } else {
         std::vector<float> t32(twd.begin(), twd.end()), s32(spd.begin(), spd.end());
-        if (hipMemcpy(*tw, t32.data(), (size_t)M * es, hipMemcpyHostToDevice) != hipSuccess ||
-            hipMemcpy(*spec, s32.data(), (size_t)M * es, hipMemcpyHostToDevice) != hipSuccess) {
+        if (hipMemcpyAsync(*tw, t32.data(), (size_t)M * es, hipMemcpyHostToDevice, st) != hipSuccess ||
+            hipMemcpyAsync(*spec, s32.data(), (size_t)M * es, hipMemcpyHostToDevice, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess) {
             set_error("Toeplitz path: hipMemcpy failed");
             return TWA_EHIP;
         }
