@@ -203,7 +203,7 @@ def scan_points(n_points=96, seed=0):
     return pts
 
 
-def batch_singles(twa, steps, integrator="sib"):
+def batch_singles(twa, steps, integrator="sib", precision="fp32"):
     """The 96 points of the scan one by one through the plain FP32 path only
     (the single-run side of the batched comparison, for step counts where
     both sides do not fit one run); device time of the step loops."""
@@ -212,19 +212,19 @@ def batch_singles(twa, steps, integrator="sib"):
     single_ms = 0.0
     for i, (N, w, a, dt, seed) in enumerate(pts):
         p = twa.build_pump(N, w, a)
-        r = twa.run(p, B, dt, steps, seed=seed, point=i, precision="fp32", integrator=integrator)
+        r = twa.run(p, B, dt, steps, seed=seed, point=i, precision=precision, integrator=integrator)
         single_ms += r.obs["kernel_ms"]
         p.close()
         print("[bench]   single run %d/%d (N = %d): %.1f ms" % (i + 1, len(pts), N, r.obs["kernel_ms"]),
               file=sys.stderr, flush=True)
     work = sum(B * N * steps for (N, _, _, _, _) in pts)
     flops = sum(12.0 * N * N * B * steps for (N, _, _, _, _) in pts)
-    return {"points": len(pts), "n_traj": B, "steps": steps, "precision": "fp32", "integrator": integrator,
+    return {"points": len(pts), "n_traj": B, "steps": steps, "precision": precision, "integrator": integrator,
             "single_runs_ms": single_ms, "single_rate": work / (single_ms * 1e-3), "unit": "trajectory-atom-steps/s",
             "single_tflops": flops / (single_ms * 1e-3) / 1e12}
 
 
-def batch_scan(twa, steps, integrator="sib", singles=True):
+def batch_scan(twa, steps, integrator="sib", singles=True, precision="fp32"):
     """Batched scan (grouped persistent launches, graph replay, autotuned
     tiles) against the same 96 points run one by one through the plain FP32
     path, and one by one through the Toeplitz path; device time of the step
@@ -233,7 +233,7 @@ def batch_scan(twa, steps, integrator="sib", singles=True):
     pts = scan_points()
     B = 512
     t0 = time.time()
-    res = twa.run_batch(pts, B, steps, precision="fp32", integrator=integrator,
+    res = twa.run_batch(pts, B, steps, precision=precision, integrator=integrator,
                         progress=max(1000, steps // 20))
     torch.cuda.synchronize()
     batch_wall = time.time() - t0
@@ -241,12 +241,16 @@ def batch_scan(twa, steps, integrator="sib", singles=True):
     work = sum(B * N * steps for (N, _, _, _, _) in pts)
     flops = sum(12.0 * N * N * B * steps for (N, _, _, _, _) in pts)
     crit = [r["step_criterion"] for r in res]
-    out = {"points": len(pts), "n_traj": B, "steps": steps, "precision": "fp32", "integrator": integrator,
+    peak = PEAK_TFLOPS["bf16" if precision == "bf16x3" else precision]
+    # split BF16 performs three BF16 products per contraction value: its
+    # MFMA flops are 3x the algorithmic ones (the rate below is algorithmic)
+    out = {"points": len(pts), "n_traj": B, "steps": steps, "precision": precision, "integrator": integrator,
            "N_list": [p[0] for p in pts], "step_criterion_min_max": [min(crit), max(crit)],
            "tile_configs": sorted(set(r["tile_config"] for r in res)),
            "batched_ms": batch_ms, "batched_rate": work / (batch_ms * 1e-3), "unit": "trajectory-atom-steps/s",
            "batched_tflops": flops / (batch_ms * 1e-3) / 1e12,
            "batched_frac_fp32_peak": flops / (batch_ms * 1e-3) / 1e12 / PEAK_TFLOPS["fp32"],
+           "batched_frac_own_peak": (3.0 if precision == "bf16x3" else 1.0) * flops / (batch_ms * 1e-3) / 1e12 / peak,
            "batch_wall_s_incl_pumps_and_tuning": batch_wall,
            "max_norm_dev_max": max(r["max_norm_dev"] for r in res)}
     if singles:
@@ -254,7 +258,7 @@ def batch_scan(twa, steps, integrator="sib", singles=True):
         toep_ms = 0.0
         for i, (N, w, a, dt, seed) in enumerate(pts):
             p = twa.build_pump(N, w, a)
-            r = twa.run(p, B, dt, steps, seed=seed, point=i, precision="fp32", integrator=integrator)
+            r = twa.run(p, B, dt, steps, seed=seed, point=i, precision=precision, integrator=integrator)
             single_ms += r.obs["kernel_ms"]
             p.close()
             lt = twa.build_pump_toeplitz(N, w, a)
@@ -263,6 +267,29 @@ def batch_scan(twa, steps, integrator="sib", singles=True):
         out.update({"single_runs_ms": single_ms, "toeplitz_single_runs_ms": toep_ms,
                     "speedup_batched_vs_single": single_ms / batch_ms,
                     "speedup_toeplitz_vs_single": single_ms / toep_ms})
+    return out
+
+
+def batch_precision_check(twa, steps, integrator="sib"):
+    """The 96-point scan for `steps` steps in FP64, FP32 and split BF16 at
+    the same noise: per point the relative difference of <S+S-> and g2
+    against FP64, and in units of the point's standard error; the largest
+    over the points, and the device time of each."""
+    pts = scan_points()
+    B = 512
+    runs = {}
+    for prec in ("fp64", "fp32", "bf16x3"):
+        print("[bench]   scan in %s, %d steps" % (prec, steps), file=sys.stderr, flush=True)
+        runs[prec] = twa.run_batch(pts, B, steps, precision=prec, integrator=integrator,
+                                   progress=max(500, steps // 4))
+    ref = runs["fp64"]
+    out = {"points": len(pts), "n_traj": B, "steps": steps, "integrator": integrator, "modes": {}}
+    for prec in ("fp32", "bf16x3"):
+        rel = {k: max(abs(a[k] - b[k]) / abs(b[k]) for a, b in zip(runs[prec], ref)) for k in ("SpSm", "g2")}
+        se = {k: max(abs(a[k] - b[k]) / b[k + "_se"] for a, b in zip(runs[prec], ref)) for k in ("SpSm", "g2")}
+        out["modes"][prec] = {"max_rel_error_vs_fp64": rel, "max_error_vs_fp64_in_se": se,
+                              "batched_ms": runs[prec][0]["kernel_ms"]}
+    out["modes"]["fp64"] = {"batched_ms": ref[0]["kernel_ms"]}
     return out
 
 
@@ -506,7 +533,11 @@ def main():
     ap.add_argument("--batch-singles", action="store_true",
                     help="with --batch-scan: also run the 96 points one by one (dense and Toeplitz)")
     ap.add_argument("--batch-singles-only", type=int, default=0,
-                    help="run only the 96 points one by one (dense FP32) for this many steps")
+                    help="run only the 96 points one by one (dense) for this many steps")
+    ap.add_argument("--batch-precision", default="fp32", choices=["fp32", "bf16x3"],
+                    help="contraction precision of the batched scan and its single runs")
+    ap.add_argument("--batch-precision-check", type=int, default=0,
+                    help="the scan for this many steps in FP64, FP32 and split BF16: errors against FP64")
     ap.add_argument("--copy-calibration", action="store_true", help="one 1 GiB device copy, then exit")
     ap.add_argument("--toeplitz-only", action="store_true", help="the Toeplitz profiling workload, then exit")
     args = ap.parse_args()
@@ -623,10 +654,14 @@ def main():
         print("[bench]   " + json.dumps(line["two_time"]), file=sys.stderr, flush=True)
     if args.batch_scan > 0:
         print("[bench] batched scan, 96 points, %d steps" % args.batch_scan, file=sys.stderr, flush=True)
-        line["batch_scan"] = batch_scan(twa, args.batch_scan, singles=args.batch_singles)
+        line["batch_scan"] = batch_scan(twa, args.batch_scan, singles=args.batch_singles,
+                                        precision=args.batch_precision)
     if args.batch_singles_only > 0:
         print("[bench] the 96 scan points one by one, %d steps" % args.batch_singles_only, file=sys.stderr, flush=True)
-        line["batch_singles"] = batch_singles(twa, args.batch_singles_only)
+        line["batch_singles"] = batch_singles(twa, args.batch_singles_only, precision=args.batch_precision)
+    if args.batch_precision_check > 0:
+        print("[bench] scan precision check, %d steps" % args.batch_precision_check, file=sys.stderr, flush=True)
+        line["batch_precision_check"] = batch_precision_check(twa, args.batch_precision_check)
     if not args.no_adjoint:
         print("[bench] adjoint cost ratio (N=2000, FP32)", file=sys.stderr, flush=True)
         line["adjoint"] = adjoint_cost(twa, steps=args.adjoint_steps)

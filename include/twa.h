@@ -371,7 +371,8 @@ typedef struct twa_batch_opts {
     int64_t burnin;          /* < 0: n_steps / 2                                  */
     double gamma;
     double s0z;
-    int32_t precision;       /* TWA_PREC_FP64 / FP32 / BF16 / FP16               */
+    int32_t precision;       /* TWA_PREC_FP64 / FP32 / BF16 / FP16, or BF16X3    */
+                             /* (split BF16: n_lags must be 0)                   */
     int32_t use_graph;       /* capture the step loop in hipGraphs (default 1)   */
     int32_t steps_per_graph; /* steps captured per graph replay (<= 0: 16)       */
     const char* tune_cache;  /* autotuner cache file (NULL: no cache)            */
@@ -393,7 +394,7 @@ typedef struct twa_batch_opts {
 } twa_batch_opts;
 
 /* Defaults: 512 trajectories, 1000 steps, burn-in n_steps/2, gamma 1, s0z +1,
- * FP32, graphs of 16 steps, no cache, null stream, Heun, norm_tol 1e-2, no
+ * FP32, graphs of 16 steps, no cache, own stream, Heun, norm_tol 1e-2, no
  * lags, kappa 1/4, autotuned tiles, silent, no per-point arrays. */
 TWA_API void twa_batch_opts_default(twa_batch_opts* o);
 

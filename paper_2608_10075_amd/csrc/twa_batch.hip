@@ -69,13 +69,16 @@ __global__ void noise_grouped_kernel(const PointDesc* __restrict__ pd, const int
     box_muller(w.x, w.y, z0, z1);
     box_muller(w.z, w.w, z2, z3);
     const int64_t i = 2 * m;
-    G* cx = static_cast<G*>(d.Xop) + opcol(k, 0) * 2 * d.P + d.P;
-    G* cy = static_cast<G*>(d.Xop) + opcol(k, 1) * 2 * d.P + d.P;
-    cx[i] = Prec<PREC>::to_g(z0);
-    cy[i] = Prec<PREC>::to_g(z1);
+    // operand column: [s ; zeta], each block P long, or in the split form
+    // (hi, lo, hi) blocks of P each for s and then for zeta
+    constexpr int SPL = Prec<PREC>::SPLIT;
+    G* cx = static_cast<G*>(d.Xop) + opcol(k, 0) * 2 * d.P * SPL + d.P * SPL;
+    G* cy = static_cast<G*>(d.Xop) + opcol(k, 1) * 2 * d.P * SPL + d.P * SPL;
+    put_op<PREC>(cx + i, d.P, z0);
+    put_op<PREC>(cy + i, d.P, z1);
     if (i + 1 < d.N) {
-        cx[i + 1] = Prec<PREC>::to_g(z2);
-        cy[i + 1] = Prec<PREC>::to_g(z3);
+        put_op<PREC>(cx + i + 1, d.P, z2);
+        put_op<PREC>(cy + i + 1, d.P, z3);
     }
     if (m == 0) {
         const U4 v = philox4x32_10(U4{0u, (uint32_t)k, n, TAG_COLLECTIVE | (d.point << 8)}, d.key0, d.key1);
@@ -329,8 +332,12 @@ int bucket_step(Bucket& bk, int cur, const StepKind& k, hipStream_t st) {
             hipLaunchKernelGGL(noise_grouped_kernel<TWA_PREC_FP16>, dim3(nb), dim3(256), 0, st, bk.d_pd, bk.d_bstart,
                                np, (const int64_t*)bk.step);
             break;
+        case TWA_PREC_BF16X3:
+            hipLaunchKernelGGL(noise_grouped_kernel<TWA_PREC_BF16X3>, dim3(nb), dim3(256), 0, st, bk.d_pd,
+                               bk.d_bstart, np, (const int64_t*)bk.step);
+            break;
         default:
-            set_error("twa_run_batch: precision must be FP64, FP32, BF16 or FP16");
+            set_error("twa_run_batch: precision must be FP64, FP32, BF16, FP16 or split BF16");
             return TWA_EINVAL;
     }
     TWA_HIP_CHECK(hipGetLastError());
@@ -520,8 +527,12 @@ int run_batch(const twa_point* pts, int np, const twa_batch_opts* o, twa_observa
         return TWA_EINVAL;
     }
     if (o->precision != TWA_PREC_FP64 && o->precision != TWA_PREC_FP32 && o->precision != TWA_PREC_BF16 &&
-        o->precision != TWA_PREC_FP16) {
-        set_error("twa_run_batch: precision must be FP64, FP32, BF16 or FP16");
+        o->precision != TWA_PREC_FP16 && o->precision != TWA_PREC_BF16X3) {
+        set_error("twa_run_batch: precision must be FP64, FP32, BF16, FP16 or split BF16");
+        return TWA_EINVAL;
+    }
+    if (o->precision == TWA_PREC_BF16X3 && o->n_lags > 0) {
+        set_error("twa_run_batch: the split-BF16 precision runs the forward step without lags (n_lags must be 0)");
         return TWA_EINVAL;
     }
     if (o->tile_config >= 0 && ((o->tile_config > 3 && o->tile_config != 7) ||

@@ -60,6 +60,7 @@ int grouped_prepare(const std::vector<Geometry>& gs, const std::vector<EnsembleB
         case TWA_PREC_BF16: return grouped_prepare_p<TWA_PREC_BF16>(gs, bs, cs, step, tangents, pl, st);
         case TWA_PREC_FP16: return grouped_prepare_p<TWA_PREC_FP16>(gs, bs, cs, step, tangents, pl, st);
         case TWA_PREC_FP64: return grouped_prepare_p<TWA_PREC_FP64>(gs, bs, cs, step, tangents, pl, st);
+        case TWA_PREC_BF16X3: return grouped_prepare_p<TWA_PREC_BF16X3>(gs, bs, cs, step, tangents, pl, st);
     }
     set_error("unknown precision");
     return TWA_EINVAL;
@@ -75,6 +76,7 @@ int grouped_launch(const GroupedPlan& pl, int stage, int cur, int variant, hipSt
         case TWA_PREC_BF16: return grouped_launch_p<TWA_PREC_BF16>(pl, stage, cur, variant, st);
         case TWA_PREC_FP16: return grouped_launch_p<TWA_PREC_FP16>(pl, stage, cur, variant, st);
         case TWA_PREC_FP64: return grouped_launch_p<TWA_PREC_FP64>(pl, stage, cur, variant, st);
+        case TWA_PREC_BF16X3: return grouped_launch_p<TWA_PREC_BF16X3>(pl, stage, cur, variant, st);
     }
     set_error("unknown precision");
     return TWA_EINVAL;

@@ -52,8 +52,10 @@ def _oracle(pt, index, B, T, burnin, **kw):
     return otwa.run(cfg, opump.build_pump(N, w, a))
 
 
+# split BF16: 1e-4, the bound of its single-run parity tests (each operand to
+# 2^-17 relative, the dropped lo x lo product below 2^-18)
 @pytest.mark.parametrize("prec,tile,tol", [("fp64", -1, 1e-10), ("fp32", -1, 1e-5), ("fp32", 7, 1e-5),
-                                           ("fp32", 2, 1e-5)])
+                                           ("fp32", 2, 1e-5), ("bf16x3", -1, 1e-4), ("bf16x3", 7, 1e-4)])
 def test_batch_points_match_oracle(twa, prec, tile, tol):
     """Each point of a batch spanning the three N buckets and reaching the
     scan's largest N against the FP64 oracle per trajectory: window moments
@@ -94,7 +96,7 @@ def test_batch_two_time_matches_oracle(twa, prec, tile, tol):
         assert r.obs["n_lags"] == L and r.obs["lag_stride"] == stride
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "bf16x3"])
 def test_batch_equals_single_runs(twa, prec, tmp_path):
     pts = _points(9) + [(1300, 1.0, 1.0, 2e-5, 500)]
     B, T = 40, 60
@@ -130,7 +132,7 @@ def test_batch_rejects_bad_input(twa):
     with pytest.raises(twa.TWAError):
         twa.run_batch([(10, -1.0, 1.0, 1e-3, 0)], 8, 10)
     with pytest.raises(twa.TWAError):
-        twa.run_batch([(10, 1.0, 1.0, 1e-3, 0)], 8, 10, precision="bf16x3")
+        twa.run_batch([(10, 1.0, 1.0, 1e-3, 0)], 8, 10, burnin=5, precision="bf16x3", n_lags=4)
     with pytest.raises(twa.TWAError):
         twa.run_batch([(10, 1.0, 1.0, 1e-3, 0)], 8, 10, tile_config=7, precision="fp64")
     with pytest.raises(twa.TWAError):
