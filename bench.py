@@ -435,16 +435,23 @@ def threshold_vs_scan(twa, N=2000, alpha=1.0, B=2048, dt=1e-4, T=2048):
     out = {"config": {"N": N, "alpha": alpha, "n_traj": B, "dt": dt, "n_steps": T, "precision": "fp32"},
            "objective": "spsm_n", "target": target, "bracket": [lo, hi], "forward_run_s": fwd,
            "bisection_forward_runs_same_tol": n_bisect}
-    for mode in ("forward", "adjoint"):
+    # Newton with forward- or reverse-mode derivatives in FP32, and with the
+    # forward mode in split BF16 (FP32-class accuracy), all against FP32
+    # bisection
+    for name, mode, prec in (("forward", "forward", "fp32"), ("adjoint", "adjoint", "fp32"),
+                             ("forward_bf16x3", "forward", "bf16x3")):
         torch.cuda.synchronize()
         t0 = time.time()
         w_root, f_root, it = twa.find_threshold(N, alpha, B, dt, T, 0, objective="spsm_n", target=target, w_lo=lo,
-                                                w_hi=hi, tol_w=tol, precision="fp32", burnin=burn, norm_tol=-1,
+                                                w_hi=hi, tol_w=tol, precision=prec, burnin=burn, norm_tol=-1,
                                                 derivative=mode)
         torch.cuda.synchronize()
         el = time.time() - t0
-        out[mode] = {"w_root": w_root, "residual": f_root, "gradient_evaluations": it, "newton_s": el,
-                     "speedup_vs_bisection": n_bisect * fwd / el}
+        out[name] = {"w_root": w_root, "residual": f_root, "gradient_evaluations": it, "newton_s": el,
+                     "precision": prec, "speedup_vs_bisection": n_bisect * fwd / el}
+        print("[bench]   Newton (%s, %s): w = %.9g in %.1f s" % (mode, prec, w_root, el), file=sys.stderr, flush=True)
+    out["forward_bf16x3"]["w_root_rel_diff_vs_fp32"] = abs(out["forward_bf16x3"]["w_root"] - out["forward"]["w_root"]) / \
+        out["forward"]["w_root"]
     return out
 
 

@@ -448,8 +448,9 @@ TWA_API int twa_adjoint(const twa_params* p, int64_t n_traj, double dt, int64_t 
  * the contraction output of a stage, Q its noise part).  About 5/3 of a
  * forward run in contraction work, no checkpoint store; the cheaper choice
  * for one parameter (the threshold search in w).  Requires a pump from
- * twa_build_pump with w > 0; Heun, no lags, precision FP64 / FP32 / BF16 /
- * FP16.  grads: host, 3 doubles.  Errors as twa_adjoint.
+ * twa_build_pump with w > 0; Heun, no lags, any precision (split BF16
+ * included: the tangent's operands in the hi, lo, hi form).  grads: host,
+ * 3 doubles.  Errors as twa_adjoint.
  */
 TWA_API int twa_tangent_w(const twa_params* p, int64_t n_traj, double dt, int64_t n_steps, uint64_t seed,
                           twa_observables* out, double* grads);

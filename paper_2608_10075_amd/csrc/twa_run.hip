@@ -335,8 +335,8 @@ int alloc_buffers(const Geometry& g, bool tangents, int64_t L, int J, EnsembleBu
         TWA_A(b.lag, (size_t)L * J * 6 * sizeof(double))
     }
     if (tangents) {
-        TWA_A(b.tXop, 2 * C2 * P * ge)
-        TWA_A(b.tDop, 2 * C2 * P * ge)
+        TWA_A(b.tXop, 2 * C2 * P * ge * spl)
+        TWA_A(b.tDop, 2 * C2 * P * ge * spl)
         TWA_A(b.ts[0], 2 * 3 * Bp * P * se)
         TWA_A(b.ts[1], 2 * 3 * Bp * P * se)
         TWA_A(b.tdlt, 2 * 3 * Bp * P * se)

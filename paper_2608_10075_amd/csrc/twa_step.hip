@@ -45,6 +45,7 @@ int launch_gemm_call(const Geometry& g, const GemmCall& c, hipStream_t st) {
         case TWA_PREC_FP32: return launch_call_p<TWA_PREC_FP32>(g, c, st);
         case TWA_PREC_BF16: return launch_call_p<TWA_PREC_BF16>(g, c, st);
         case TWA_PREC_FP16: return launch_call_p<TWA_PREC_FP16>(g, c, st);
+        case TWA_PREC_BF16X3: return launch_call_p<TWA_PREC_BF16X3>(g, c, st);
     }
     set_error("unknown precision");
     return TWA_EINVAL;

@@ -810,8 +810,9 @@ __device__ __forceinline__ void stage_tile(const GemmArgs<PREC>& a, const int mt
                 st4(ty + off, ax4);
                 st4(ty + SP + off, ay4);
                 G* tdo = a.tDop + cp * a.t_op_copy;
-                stg4<PREC>(tdo + opcol(k, 0) * P + i0, ex);
-                stg4<PREC>(tdo + opcol(k, 1) * P + i0, ey);
+                constexpr int SPLT = Prec<PREC>::SPLIT;
+                stg4s<PREC>(tdo + opcol(k, 0) * P * SPLT + i0, P, ex);
+                stg4s<PREC>(tdo + opcol(k, 1) * P * SPLT + i0, P, ey);
             } else if constexpr (KD == KIND_STORE) {
                 S ox[4], oy[4];
                 if (a.Sin) {
@@ -966,8 +967,8 @@ __device__ __forceinline__ void stage_tile(const GemmArgs<PREC>& a, const int mt
                 st4(tn + SP + off, nv);
                 st4(tn + 2 * SP + off, nw);
                 G* txo = a.Xnext + cp * a.t_op_copy;
-                stg4<PREC>(txo + opcol(k, 0) * a.ldxn + i0, nu);
-                stg4<PREC>(txo + opcol(k, 1) * a.ldxn + i0, nv);
+                stg4s<PREC>(txo + opcol(k, 0) * a.ldxn + i0, P, nu);
+                stg4s<PREC>(txo + opcol(k, 1) * a.ldxn + i0, P, nv);
             }
             // the partial sums are formed inside their block (an empty asm pins
             // each sum in a register here): sunk to the end of the group, they
@@ -1094,14 +1095,20 @@ template <int PREC, int CFG>
 static int dispatch_kind(const GemmArgs<PREC>& a, int stage, int kind, int64_t P, int64_t C2, int ncopy,
                          hipStream_t st) {
     if constexpr (Prec<PREC>::SPLIT == 3) {
-        // the split form runs the forward step only
+        // the split form runs the forward step and the forward-mode tangent
+        // (with the predictor that keeps its noise part)
         if (kind == KIND_PRIMAL)
             return stage == 1 ? launch_kernel<PREC, CFG, 1, KIND_PRIMAL>(a, P, C2, ncopy, st)
                               : launch_kernel<PREC, CFG, 2, KIND_PRIMAL>(a, P, C2, ncopy, st);
         if (kind == KIND_SIB)
             return stage == 1 ? launch_kernel<PREC, CFG, 1, KIND_SIB>(a, P, C2, ncopy, st)
                               : launch_kernel<PREC, CFG, 2, KIND_SIB>(a, P, C2, ncopy, st);
-        set_error("split BF16: forward primal or semi-implicit steps only");
+        if (kind == KIND_TANGENT)
+            return stage == 1 ? launch_kernel<PREC, CFG, 1, KIND_TANGENT>(a, P, C2, ncopy, st)
+                              : launch_kernel<PREC, CFG, 2, KIND_TANGENT>(a, P, C2, ncopy, st);
+        if (kind == (KIND_PRIMAL | KIND_Q_SNAPSHOT) && stage == 1)
+            return launch_kernel<PREC, CFG, 1, KIND_PRIMAL | KIND_Q_SNAPSHOT>(a, P, C2, ncopy, st);
+        set_error("split BF16: forward primal, semi-implicit and tangent steps only");
         return TWA_EINVAL;
     } else {
         if (stage == 1) {
@@ -1181,7 +1188,7 @@ static GemmArgs<PREC> make_args(const Geometry& g, const EnsembleBuffers& b, con
     a.t_state_copy = 3 * Bp * P;
     a.t_y_copy = 2 * Bp * P;
     a.t_part_copy = 3 * g.nmt * Bp;
-    a.t_op_copy = g.C2 * P;
+    a.t_op_copy = g.C2 * P * SPL;
     if (!tangent) {
         if (stage == 1) {
             a.X = static_cast<const G*>(b.Xop);
@@ -1205,9 +1212,9 @@ static GemmArgs<PREC> make_args(const Geometry& g, const EnsembleBuffers& b, con
         a.t_dlt = static_cast<S*>(b.tdlt);
         a.tY = static_cast<S*>(b.tY);
         a.tDop = static_cast<G*>(b.tDop);
-        a.x_copy = g.C2 * P;
-        a.K = P;
-        a.ldx = P;
+        a.x_copy = g.C2 * P * SPL;
+        a.K = P * SPL;
+        a.ldx = P * SPL;
         if (stage == 1) {
             a.X = static_cast<const G*>(b.tXop);
             a.part_prim = static_cast<const S*>(b.part[0]);
@@ -1219,7 +1226,7 @@ static GemmArgs<PREC> make_args(const Geometry& g, const EnsembleBuffers& b, con
             a.tpart_in = static_cast<const S*>(b.tpart[1]);
             a.part_out = static_cast<S*>(b.tpart[0]);
             a.Xnext = static_cast<G*>(b.tXop);
-            a.ldxn = P;
+            a.ldxn = P * SPL;
         }
     }
     return a;
@@ -1258,7 +1265,7 @@ int launch_call_p(const Geometry& g, const GemmCall& c, hipStream_t st) {
     a.Y = static_cast<S*>(c.Y);
     a.Y2out = static_cast<S*>(c.Y2out);
     a.Dop = static_cast<G*>(c.Dop);
-    a.ldd = g.P;
+    a.ldd = g.P * Prec<PREC>::SPLIT;
     a.coh = 0;
     a.Xnext = static_cast<G*>(c.Xnext);
     a.ldxn = c.ldxn;
@@ -1275,12 +1282,12 @@ int launch_call_p(const Geometry& g, const GemmCall& c, hipStream_t st) {
     a.t_state_copy = 3 * g.Bp * g.P;
     a.t_y_copy = 2 * g.Bp * g.P;
     a.t_part_copy = 3 * g.nmt * g.Bp;
-    a.t_op_copy = g.C2 * g.P;
+    a.t_op_copy = g.C2 * g.P * Prec<PREC>::SPLIT;
     a.step = c.step;
     a.Sin = static_cast<const S*>(c.Sin);
     a.Sout = static_cast<S*>(c.Sout);
     a.store_sign = (S)c.store_sign;
-    a.kq = (int)(g.P / g.kt);
+    a.kq = (int)(g.P * Prec<PREC>::SPLIT / g.kt);   // K stage where the noise columns start
     a.Y2in = static_cast<const S*>(c.Y2in);
     a.Qin = static_cast<const S*>(c.Qin);
     a.YA = static_cast<const S*>(c.YA);

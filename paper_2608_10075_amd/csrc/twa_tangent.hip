@@ -72,9 +72,8 @@ int run_tangent_w(const twa_params* p, int64_t n_traj, double dt, int64_t n_step
         return TWA_EINVAL;
     }
     if (p->integrator != TWA_INT_HEUN || p->n_lags > 0 || p->pump_path != TWA_PUMP_DENSE ||
-        (p->precision != TWA_PREC_FP64 && p->precision != TWA_PREC_FP32 && p->precision != TWA_PREC_BF16 &&
-         p->precision != TWA_PREC_FP16)) {
-        set_error("twa_tangent_w: Heun, dense pump, no lags, precision FP64, FP32, BF16 or FP16");
+        p->precision < TWA_PREC_FP64 || p->precision > TWA_PREC_BF16X3) {
+        set_error("twa_tangent_w: Heun, dense pump, no lags, a known precision");
         return TWA_EINVAL;
     }
     const int64_t N = pump->N, B = n_traj;
@@ -90,6 +89,7 @@ int run_tangent_w(const twa_params* p, int64_t n_traj, double dt, int64_t n_step
     }
     Geometry g = make_geometry(p->precision, cfg, N, B);
     const int J = (int)std::min<int64_t>(32, B);
+    const int64_t KP = g.P * operand_split(p->precision);   // K extent of one operand block (split: hi, lo, hi)
     const size_t se = (size_t)state_elt_bytes(p->precision);
     const size_t plane = (size_t)g.Bp * g.P * se;
     hipStream_t st = (hipStream_t)p->stream;
@@ -153,27 +153,27 @@ int run_tangent_w(const twa_params* p, int64_t n_traj, double dt, int64_t n_step
     for (int64_t n = 0; n < n_steps; ++n) {
         TWA_TRY(launch_noise(g, b, c, st));
         GemmCall p1;   // predictor, also storing its noise part Q
-        p1.kind = KIND_PRIMAL_WITH_Q; p1.stage = 1; p1.A = b.A; p1.X = b.Xop; p1.ldx = 2 * g.P;
-        p1.K = 2 * g.P; p1.c1 = c.c1; p1.c2 = c.c2; p1.s_cur = b.s[cur]; p1.dlt = b.dlt; p1.Y = b.Y;
+        p1.kind = KIND_PRIMAL_WITH_Q; p1.stage = 1; p1.A = b.A; p1.X = b.Xop; p1.ldx = 2 * KP;
+        p1.K = 2 * KP; p1.c1 = c.c1; p1.c2 = c.c2; p1.s_cur = b.s[cur]; p1.dlt = b.dlt; p1.Y = b.Y;
         p1.Dop = b.Dop; p1.Sout = Q; p1.part_prim = b.part[0]; p1.part_out = b.part[1]; p1.g = b.g; p1.step = b.step;
         TWA_TRY(launch_gemm_call(g, p1, st));
         GemmCall t1;   // tangent predictor with the w-source
-        t1.kind = 1; t1.stage = 1; t1.ncopy = 1; t1.A = b.A; t1.X = b.tXop; t1.ldx = g.P;
-        t1.K = g.P; t1.c1 = c.c1; t1.c2 = c.c2; t1.s_cur = b.s[cur]; t1.Y = b.Y; t1.g = b.g;
+        t1.kind = 1; t1.stage = 1; t1.ncopy = 1; t1.A = b.A; t1.X = b.tXop; t1.ldx = KP;
+        t1.K = KP; t1.c1 = c.c1; t1.c2 = c.c2; t1.s_cur = b.s[cur]; t1.Y = b.Y; t1.g = b.g;
         t1.part_prim = b.part[0]; t1.tpart_in = b.tpart[0]; t1.part_out = b.tpart[1]; t1.t_cur = b.ts[cur];
         t1.t_dlt = b.tdlt; t1.tY = b.tY; t1.tDop = b.tDop; t1.Qin = Q; t1.inv_w = inv_w;
         TWA_TRY(launch_gemm_call(g, t1, st));
         GemmCall p2;   // corrector, its field Y2 stored in place of Y1
-        p2.kind = 0; p2.stage = 2; p2.A = b.A; p2.X = b.Dop; p2.ldx = g.P; p2.K = g.P;
+        p2.kind = 0; p2.stage = 2; p2.A = b.A; p2.X = b.Dop; p2.ldx = KP; p2.K = KP;
         p2.c1 = c.c1; p2.c2 = c.c2; p2.s_cur = b.s[cur]; p2.s_next = b.s[1 - cur]; p2.dlt = b.dlt; p2.Y = b.Y;
-        p2.store_y2 = 1; p2.part_prim = b.part[1]; p2.part_out = b.part[0]; p2.Xnext = b.Xop; p2.ldxn = 2 * g.P;
+        p2.store_y2 = 1; p2.part_prim = b.part[1]; p2.part_out = b.part[0]; p2.Xnext = b.Xop; p2.ldxn = 2 * KP;
         p2.g = b.g; p2.step = b.step;
         TWA_TRY(launch_gemm_call(g, p2, st));
         GemmCall t2;   // tangent corrector with the w-source at the corrector's field
-        t2.kind = 1; t2.stage = 2; t2.ncopy = 1; t2.A = b.A; t2.X = b.tDop; t2.ldx = g.P;
-        t2.K = g.P; t2.c1 = c.c1; t2.c2 = c.c2; t2.s_cur = b.s[cur]; t2.dlt = b.dlt; t2.Y = b.Y; t2.g = b.g;
+        t2.kind = 1; t2.stage = 2; t2.ncopy = 1; t2.A = b.A; t2.X = b.tDop; t2.ldx = KP;
+        t2.K = KP; t2.c1 = c.c1; t2.c2 = c.c2; t2.s_cur = b.s[cur]; t2.dlt = b.dlt; t2.Y = b.Y; t2.g = b.g;
         t2.part_prim = b.part[1]; t2.tpart_in = b.tpart[1]; t2.part_out = b.tpart[0]; t2.t_cur = b.ts[cur];
-        t2.t_next = b.ts[1 - cur]; t2.t_dlt = b.tdlt; t2.tY = b.tY; t2.Xnext = b.tXop; t2.ldxn = g.P; t2.Qin = Q;
+        t2.t_next = b.ts[1 - cur]; t2.t_dlt = b.tdlt; t2.tY = b.tY; t2.Xnext = b.tXop; t2.ldxn = KP; t2.Qin = Q;
         t2.inv_w = inv_w;
         TWA_TRY(launch_gemm_call(g, t2, st));
         if (n + 1 > burnin) {
