@@ -29,7 +29,7 @@ def test_tangent_matches_oracle_gradient(twa, prec, N, B, cfg, tol):
     """FP64 to rounding order; FP32 2e-3 (each step rounds the tangent's
     operands to FP32, accumulated over the window); split BF16 under the
     same bound: its operands carry 2^-17 instead of 2^-24, 128x FP32's
-    rounding (measured 4e-6 against FP32's 1e-7 scale)."""
+    rounding (measured at most 7e-6)."""
     w, alpha, seed, T = 2.0, 1.0, 7, 240
     dt = 0.1 / max(N, 20)
     burn = T // 2
