@@ -151,13 +151,26 @@ def adjoint_cost(twa, steps=2048, reps=1):
         adj.append(t2 - t1)
         adj2.append(t3 - t2)
     f, a, a2 = min(fwd), min(adj), min(adj2)
+    # the same reverse sweep in split BF16 (FP32-class operands), against the
+    # FP32 forward run and the FP32 gradients
+    twa.adjoint(pump, B, dt, 256, seed=0, precision="bf16x3", ckpt_every=ck, objectives=("g2",), norm_tol=-1)
+    torch.cuda.synchronize()
+    t4 = time.time()
+    _, g3 = twa.adjoint(pump, B, dt, steps, seed=0, precision="bf16x3", ckpt_every=ck, objectives=("g2",),
+                        norm_tol=-1)
+    torch.cuda.synchronize()
+    a3 = time.time() - t4
+    print("[bench]   adjoint for g2 in split BF16: %.1f s" % a3, file=sys.stderr, flush=True)
+    split = {"adjoint_s": a3, "ratio_vs_fp32_forward": a3 / f, "speedup_vs_fp32_adjoint": a / a3,
+             "gradients": {k: v for k, v in g3.items() if k.startswith("d_g2")},
+             "rel_diff_vs_fp32": {k: abs(g3[k] - grads[k]) / abs(grads[k]) for k in ("d_g2_dw", "d_g2_dalpha")}}
     grads = {k: v for k, v in grads.items() if k.startswith("d_g2")}
     return {"ratio": a / f, "forward_s": f, "adjoint_s": a, "steps": steps, "objective": "g2",
             "ratio_both_objectives": a2 / f,
             "config": {"N": N, "alpha": alpha, "w": w, "n_traj": B, "dt": dt, "precision": "fp32",
                        "ckpt_every": ck, "tile_config": r.obs["tile_config"], "integrator": "heun"},
             "forward_ms_per_step": 1e3 * f / steps, "adjoint_ms_per_step": 1e3 * a / steps,
-            "max_norm_dev": obs["max_norm_dev"], "gradients": grads}
+            "max_norm_dev": obs["max_norm_dev"], "gradients": grads, "split_bf16": split}
 
 
 def gradient_check(twa, steps, prec, hs):

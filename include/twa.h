@@ -431,7 +431,9 @@ TWA_API int twa_run_batch(const twa_point* pts, int n_points, const twa_batch_op
  *   grads[0] = dSpSm/dw, grads[1] = dSpSm/dalpha,
  *   grads[2] = dg2/dw,   grads[3] = dg2/dalpha.
  * The observables of the forward run are written to *out.  Requires a pump
- * from twa_build_pump with w > 0.  Errors as twa_run.
+ * from twa_build_pump with w > 0 and the Heun integrator; precision FP64,
+ * FP32 or split BF16 (TWA_PREC_BF16X3: every contraction, forward and
+ * reverse, with its operands in the hi, lo, hi form).  Errors as twa_run.
  */
 TWA_API int twa_adjoint(const twa_params* p, int64_t n_traj, double dt, int64_t n_steps,
                         uint64_t seed, int32_t ckpt_every, twa_observables* out,

@@ -67,15 +67,16 @@ __global__ void symmetrize_kernel2(int64_t N, double* F) {
 
 __global__ void set_step_kernel(int64_t* step, int64_t v) { step[0] = v; }
 
-// write the s-part of the operand from a state
+// write the s-part of the operand from a state (split form: hi, lo, hi
+// blocks of P each)
 template <int PREC>
 __global__ void state_to_op_kernel(const typename Prec<PREC>::S* s, int64_t P, int64_t Bp,
                                    typename Prec<PREC>::G* Xop) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= Bp * P) return;
-    const int64_t k = t / P, i = t % P, SP = Bp * P;
-    Xop[opcol(k, 0) * 2 * P + i] = Prec<PREC>::to_g(s[t]);
-    Xop[opcol(k, 1) * 2 * P + i] = Prec<PREC>::to_g(s[SP + t]);
+    const int64_t k = t / P, i = t % P, SP = Bp * P, ld = 2 * P * Prec<PREC>::SPLIT;
+    put_op<PREC>(Xop + opcol(k, 0) * ld + i, P, s[t]);
+    put_op<PREC>(Xop + opcol(k, 1) * ld + i, P, s[SP + t]);
 }
 
 // nu2 = df/dH^T (lam/2) at the predictor state s~ = s + D, as the operand of
@@ -95,15 +96,16 @@ __global__ __launch_bounds__(256) void prep_nu2_kernel(const typename Prec<PREC>
     if (k >= Bp) return;   // uniform per wave
     const int64_t SP = Bp * P;
     const S* l = lam + (int64_t)cp * 3 * SP;
-    typename Prec<PREC>::G* o = op + (int64_t)cp * C2 * P;
+    const int64_t ld = P * Prec<PREC>::SPLIT;   // operand column pitch (split: hi, lo, hi blocks)
+    typename Prec<PREC>::G* o = op + (int64_t)cp * C2 * ld;
     S sx = 0, sy = 0;
     for (int64_t i = mt * mtile + lane; i < (mt + 1) * mtile; i += 64) {
         const int64_t e = k * P + i;
         const S px = s[e] + d[e], py = s[SP + e] + d[SP + e], pz = s[2 * SP + e] + d[2 * SP + e];
         const S ux = S(0.5) * l[e], uy = S(0.5) * l[SP + e], uz = S(0.5) * l[2 * SP + e];
         const S nx = ux * pz - uz * px, ny = uy * pz - uz * py;
-        o[opcol(k, 0) * P + i] = Prec<PREC>::to_g(nx);
-        o[opcol(k, 1) * P + i] = Prec<PREC>::to_g(ny);
+        put_op<PREC>(o + opcol(k, 0) * ld + i, P, nx);
+        put_op<PREC>(o + opcol(k, 1) * ld + i, P, ny);
         sx += nx;
         sy += ny;
     }
@@ -299,6 +301,8 @@ int adjoint_impl(const twa_params* p, int64_t n_traj, double dt, int64_t n_steps
     if (mask & 1) obj[nobj++] = 0;
     if (mask & 2) obj[nobj++] = 1;
     const size_t se = sizeof(S), ge = (size_t)gemm_elt_bytes(p->precision);
+    // K extent of one operand block: P, or 3P in the split form (hi, lo, hi)
+    const int64_t KP = g.P * Prec<PREC>::SPLIT;
     const size_t plane = (size_t)g.Bp * g.P * se;
     const size_t partsz = (size_t)3 * g.nmt * g.Bp * se;
 
@@ -356,8 +360,8 @@ int adjoint_impl(const twa_params* p, int64_t n_traj, double dt, int64_t n_steps
         size_t freeb = 0, totb = 0;
         TWA_HTRY(hipMemGetInfo(&freeb, &totb));
         const double need = (double)plane * (3.0 * (K + 1) + 13.0 * K + 3.0 * nseg + 18.0) +
-                            (double)partsz * (2.0 * K + 5 + nseg) + (double)g.C2 * g.P * ge * 7.0 +
-                            (double)g.P * 2 * g.P * ge * 2.0;
+                            (double)partsz * (2.0 * K + 5 + nseg) + (double)g.C2 * KP * ge * 7.0 +
+                            (double)g.P * 2 * KP * ge * 2.0;
         if (need > 0.9 * (double)freeb) {
             set_error("twa_adjoint: the checkpoint segment needs " + std::to_string(need / 1e9) +
                       " GB of device memory; reduce ckpt_every");
@@ -378,12 +382,12 @@ int adjoint_impl(const twa_params* p, int64_t n_traj, double dt, int64_t n_steps
     TWA_TRY(dalloc0(&m.g, (size_t)2 * g.Bp * se * K, st));
     TWA_TRY(dalloc0(&m.ckpt, plane * 3 * nseg, st));
     TWA_TRY(dalloc0(&m.ckpt_part, partsz * nseg, st));
-    TWA_TRY(dalloc0(&m.Aa, (size_t)g.P * 2 * g.P * ge, st));
+    TWA_TRY(dalloc0(&m.Aa, (size_t)g.P * 2 * KP * ge, st));
     TWA_TRY(dalloc0(&m.lam, plane * 6, st));
     TWA_TRY(dalloc0(&m.M1, plane * 6, st));
     TWA_TRY(dalloc0(&m.Rb, plane * 6, st));
-    TWA_TRY(dalloc0(&m.nu2, (size_t)2 * g.C2 * g.P * ge, st));
-    TWA_TRY(dalloc0(&m.nu1, (size_t)2 * g.C2 * g.P * ge, st));
+    TWA_TRY(dalloc0(&m.nu2, (size_t)2 * g.C2 * KP * ge, st));
+    TWA_TRY(dalloc0(&m.nu1, (size_t)2 * g.C2 * KP * ge, st));
     TWA_TRY(dalloc0(&m.nu2p, partsz * 2, st));
     TWA_TRY(dalloc0(&m.nu1p, partsz * 2, st));
     TWA_TRY(dalloc0((void**)&m.gacc, (size_t)4 * g.nmt * g.Bp * sizeof(double), st));
@@ -496,22 +500,22 @@ int adjoint_impl(const twa_params* p, int64_t n_traj, double dt, int64_t n_steps
             TWA_TRY(launch_noise(g, bj, c, st));
             GemmCall p1;   // predictor, also storing its noise part Q = -sqrt(dt) F zeta (second K half)
             p1.kind = KIND_PRIMAL_WITH_Q; p1.stage = 1; p1.A = b.A; p1.X = b.Xop;
-            p1.ldx = 2 * g.P; p1.K = 2 * g.P;
+            p1.ldx = 2 * KP; p1.K = 2 * KP;
             p1.c1 = c.c1; p1.c2 = c.c2; p1.s_cur = sj; p1.dlt = dj; p1.Y = y1j; p1.Dop = b.Dop; p1.Sout = qj;
             p1.part_prim = pSj; p1.part_out = pPj; p1.g = gj; p1.step = b.step;
             TWA_TRY(launch_gemm_call(g, p1, st));
             GemmCall sa1;  // dY1/dalpha = A_alpha [s; zeta]
-            sa1.kind = 2; sa1.stage = 1; sa1.A = m.Aa; sa1.X = b.Xop; sa1.ldx = 2 * g.P;
-            sa1.K = 2 * g.P; sa1.Sout = ya1j; sa1.store_sign = 1.0;
+            sa1.kind = 2; sa1.stage = 1; sa1.A = m.Aa; sa1.X = b.Xop; sa1.ldx = 2 * KP;
+            sa1.K = 2 * KP; sa1.Sout = ya1j; sa1.store_sign = 1.0;
             TWA_TRY(launch_gemm_call(g, sa1, st));
             GemmCall p2;
-            p2.kind = 0; p2.stage = 2; p2.A = b.A; p2.X = b.Dop; p2.ldx = g.P; p2.K = g.P;
+            p2.kind = 0; p2.stage = 2; p2.A = b.A; p2.X = b.Dop; p2.ldx = KP; p2.K = KP;
             p2.c1 = c.c1; p2.c2 = c.c2; p2.s_cur = sj; p2.s_next = sj1; p2.dlt = dj; p2.Y = y1j; p2.Y2out = y2j;
-            p2.store_y2 = 1; p2.part_prim = pPj; p2.part_out = pSj1; p2.Xnext = b.Xop; p2.ldxn = 2 * g.P; p2.g = gj;
+            p2.store_y2 = 1; p2.part_prim = pPj; p2.part_out = pSj1; p2.Xnext = b.Xop; p2.ldxn = 2 * KP; p2.g = gj;
             p2.step = b.step;
             TWA_TRY(launch_gemm_call(g, p2, st));
             GemmCall sa2;  // dY2/dalpha = dY1/dalpha + A_alpha,left D
-            sa2.kind = 2; sa2.stage = 1; sa2.A = m.Aa; sa2.X = b.Dop; sa2.ldx = g.P; sa2.K = g.P;
+            sa2.kind = 2; sa2.stage = 1; sa2.A = m.Aa; sa2.X = b.Dop; sa2.ldx = KP; sa2.K = KP;
             sa2.Sin = ya1j; sa2.Sout = ya2j; sa2.store_sign = 1.0;
             TWA_TRY(launch_gemm_call(g, sa2, st));
         }
@@ -530,15 +534,15 @@ int adjoint_impl(const twa_params* p, int64_t n_traj, double dt, int64_t n_steps
             char* gj = (char*)m.g + (size_t)j * 2 * g.Bp * se;
             TWA_TRY(prep_nu2<PREC>(g, m.lam, sj, dj, m.nu2, m.nu2p, nobj, st));
             GemmCall a2;
-            a2.kind = 3; a2.stage = 2; a2.ncopy = nobj; a2.A = b.A; a2.X = m.nu2; a2.ldx = g.P;
-            a2.x_copy = g.C2 * g.P; a2.K = g.P; a2.c1 = c.c1; a2.c2 = c.c2; a2.s_cur = sj; a2.dlt = dj; a2.Y = y1j;
+            a2.kind = 3; a2.stage = 2; a2.ncopy = nobj; a2.A = b.A; a2.X = m.nu2; a2.ldx = KP;
+            a2.x_copy = g.C2 * KP; a2.K = KP; a2.c1 = c.c1; a2.c2 = c.c2; a2.s_cur = sj; a2.dlt = dj; a2.Y = y1j;
             a2.Y2in = y2j; a2.Qin = qj; a2.YA = ya2j; a2.lam = m.lam; a2.M1 = m.M1; a2.Rb = m.Rb;
             a2.part_prim = pPj; a2.g = gj; a2.tpart_in = m.nu2p; a2.part_out = m.nu1p; a2.Xnext = m.nu1;
-            a2.ldxn = g.P; a2.gacc = m.gacc; a2.inv_w = 1.0 / pump->w;
+            a2.ldxn = KP; a2.gacc = m.gacc; a2.inv_w = 1.0 / pump->w;
             TWA_TRY(launch_gemm_call(g, a2, st));
             GemmCall a1;
-            a1.kind = 4; a1.stage = 1; a1.ncopy = nobj; a1.A = b.A; a1.X = m.nu1; a1.ldx = g.P;
-            a1.x_copy = g.C2 * g.P; a1.K = g.P; a1.c1 = c.c1; a1.c2 = c.c2; a1.s_cur = sj; a1.Y = y1j; a1.Qin = qj;
+            a1.kind = 4; a1.stage = 1; a1.ncopy = nobj; a1.A = b.A; a1.X = m.nu1; a1.ldx = KP;
+            a1.x_copy = g.C2 * KP; a1.K = KP; a1.c1 = c.c1; a1.c2 = c.c2; a1.s_cur = sj; a1.Y = y1j; a1.Qin = qj;
             a1.YA = ya1j; a1.lam = m.lam; a1.M1 = m.M1; a1.Rb = m.Rb; a1.part_prim = pSj; a1.g = gj;
             a1.tpart_in = m.nu1p; a1.gacc = m.gacc; a1.inv_w = 1.0 / pump->w;
             std::memcpy(a1.srccoef, cf, sizeof(cf));
@@ -614,7 +618,8 @@ extern "C" TWA_API int twa_adjoint(const twa_params* p, int64_t n_traj, double d
     switch (p->precision) {
         case TWA_PREC_FP64: return adjoint_impl<TWA_PREC_FP64>(p, n_traj, dt, n_steps, seed, K, out, grads);
         case TWA_PREC_FP32: return adjoint_impl<TWA_PREC_FP32>(p, n_traj, dt, n_steps, seed, K, out, grads);
+        case TWA_PREC_BF16X3: return adjoint_impl<TWA_PREC_BF16X3>(p, n_traj, dt, n_steps, seed, K, out, grads);
     }
-    set_error("twa_adjoint: precision must be TWA_PREC_FP64 or TWA_PREC_FP32");
+    set_error("twa_adjoint: precision must be TWA_PREC_FP64, TWA_PREC_FP32 or TWA_PREC_BF16X3");
     return TWA_EINVAL;
 }

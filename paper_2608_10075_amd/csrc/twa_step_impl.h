@@ -877,8 +877,8 @@ __device__ __forceinline__ void stage_tile(const GemmArgs<PREC>& a, const int mt
                 st4(a.Rb + co + SP + off, ry);
                 st4(a.Rb + co + 2 * SP + off, rz);
                 G* no = a.Xnext + cp * a.t_op_copy;
-                stg4<PREC>(no + opcol(k, 0) * a.ldxn + i0, n1x);
-                stg4<PREC>(no + opcol(k, 1) * a.ldxn + i0, n1y);
+                stg4s<PREC>(no + opcol(k, 0) * a.ldxn + i0, P, n1x);
+                stg4s<PREC>(no + opcol(k, 1) * a.ldxn + i0, P, n1y);
             } else if constexpr (KD == KIND_ADJ1) {
                 // reverse of the predictor: (mu1, R) -> lam of the step's input state
                 const int64_t co = cp * a.t_state_copy;
@@ -1108,7 +1108,10 @@ static int dispatch_kind(const GemmArgs<PREC>& a, int stage, int kind, int64_t P
                               : launch_kernel<PREC, CFG, 2, KIND_TANGENT>(a, P, C2, ncopy, st);
         if (kind == (KIND_PRIMAL | KIND_Q_SNAPSHOT) && stage == 1)
             return launch_kernel<PREC, CFG, 1, KIND_PRIMAL | KIND_Q_SNAPSHOT>(a, P, C2, ncopy, st);
-        set_error("split BF16: forward primal, semi-implicit and tangent steps only");
+        if (kind == KIND_STORE && stage == 1) return launch_kernel<PREC, CFG, 1, KIND_STORE>(a, P, C2, ncopy, st);
+        if (kind == KIND_ADJ1 && stage == 1) return launch_kernel<PREC, CFG, 1, KIND_ADJ1>(a, P, C2, ncopy, st);
+        if (kind == KIND_ADJ2 && stage == 2) return launch_kernel<PREC, CFG, 2, KIND_ADJ2>(a, P, C2, ncopy, st);
+        set_error("split BF16: unsupported step kind");
         return TWA_EINVAL;
     } else {
         if (stage == 1) {

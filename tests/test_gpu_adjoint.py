@@ -98,7 +98,7 @@ def test_adjoint_rejects_bad_arguments(twa):
         twa.adjoint(p, 8, 1e-3, 10, ckpt_every=0, norm_tol=-1)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
 def test_single_objective_sweep_equals_its_copy_of_the_joint_sweep(twa, prec):
     """Each objective is an independent copy of the reverse sweep: asking for one
     gives exactly that copy's gradients (the other entries are NaN)."""

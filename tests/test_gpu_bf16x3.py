@@ -74,8 +74,6 @@ def test_split_bf16_rejections(twa):
     with pytest.raises(twa.TWAError):
         twa.run(p, 8, 1e-3, 20, precision="bf16x3", n_lags=4, norm_tol=-1)
     with pytest.raises(twa.TWAError):
-        twa.adjoint(p, 8, 1e-3, 20, precision="bf16x3", norm_tol=-1)
-    with pytest.raises(twa.TWAError):
         twa.run_batch([(64, 1.0, 1.0, 1e-3, 0)], 8, 20, burnin=10, precision="bf16x3", n_lags=4, norm_tol=-1)
     with pytest.raises(twa.TWAError):
         twa.run(p, 8, 1e-3, 20, precision="bf16x3", pump_path="toeplitz", norm_tol=-1)

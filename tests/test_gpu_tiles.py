@@ -75,6 +75,9 @@ ADJOINT_CASES = [
     ("fp64", 3, 130, 40, 1e-8),
     ("fp32", 2, 300, 64, 2e-3),
     ("fp32", 7, 650, 130, 2e-3),
+    # split BF16: operands to 2^-17 (128x FP32's rounding) under the FP32 bound
+    ("bf16x3", 2, 300, 64, 2e-3),
+    ("bf16x3", 7, 650, 130, 2e-3),
 ]
 
 
@@ -88,11 +91,11 @@ def test_adjoint_on_tile(twa, prec, cfg, N, B, tol):
     assert obs["tile_config"] == cfg
     ref = ograd.pathwise_gradients(otwa.RunConfig(n_spin=N, w=w, alpha=alpha, n_traj=B, dt=dt, n_steps=T,
                                                   seed=seed, burnin=burn))
-    otol = 1e-10 if prec == "fp64" else 1e-5
+    otol = {"fp64": 1e-10, "fp32": 1e-5, "bf16x3": 1e-4}[prec]
     for k in ("SpSm", "g2", "Sz"):
         assert abs(obs[k] - ref[k]) <= otol * max(1.0, abs(ref[k])), (k, obs[k], ref[k])
     for k in KEYS:
         err = abs(g[k] - ref[k])
         print("  %s gpu %.10g oracle %.10g rel %.2e" % (k, g[k], ref[k], err / max(abs(ref[k]), 1e-300)))
-        atol = (1e-10 if prec == "fp64" else 1e-6) * max(1.0, abs(ref["SpSm"]))
+        atol = {"fp64": 1e-10, "fp32": 1e-6, "bf16x3": 1e-5}[prec] * max(1.0, abs(ref["SpSm"]))
         assert err <= tol * abs(ref[k]) + atol, (k, g[k], ref[k])
