@@ -30,7 +30,7 @@ Beside the headline (each skippable):
     BF16 (hi + lo), BF16 and FP16: time per step, speed-up over FP32 and the
     error of <S^z>, <S+S-> and g2 against FP64 (same noise);
   * ``linewidth_precision``: the linewidth of the two-time correlation on the
-    N = 1000 workload in FP64, FP32, BF16 and FP16;
+    N = 1000 workload in FP64, FP32, split BF16, BF16 and FP16;
   * ``toeplitz_path``: the headline workload through the circulant embedding
     of Eq. (2), FP32;
   * ``adjoint``: the second half of the metric, wall(twa_adjoint for
@@ -356,15 +356,16 @@ def precision_table(twa, pump, B, dt, integrator, T=2000):
 def linewidth_precision(twa, N=1000, w=1.0, alpha=1.0, B=1024, dt=1e-4, T=4000, lags=500):
     """Linewidth (FWHM of the spectrum of the two-time correlation, from the two
     tangent-linear response copies) of the N = 1000 workload in FP64, FP32,
-    BF16 and FP16 contractions, same noise, and its error against FP64; Heun
-    (the response copies are defined for it), window over the last half."""
+    split BF16, BF16 and FP16 contractions, same noise, and its error against
+    FP64; Heun (the response copies are defined for it), window over the last
+    half."""
     pump = twa.build_pump(N, w, alpha)
     burn = T // 2
     stride = max(1, (T - burn) // lags)
     out = {"config": {"N": N, "w": w, "alpha": alpha, "n_traj": B, "dt": dt, "n_steps": T, "burnin": burn,
                       "n_lags": lags, "lag_stride": stride}, "modes": {}}
     res = {}
-    for prec in ("fp64", "fp32", "bf16", "fp16"):
+    for prec in ("fp64", "fp32", "bf16x3", "bf16", "fp16"):
         r = twa.run(pump, B, dt, T, seed=0, precision=prec, burnin=burn, n_lags=lags, lag_stride=stride, norm_tol=-1)
         res[prec] = r.obs
     ref = res["fp64"]

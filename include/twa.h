@@ -75,8 +75,9 @@ extern "C" {
                             /* product formed as Ahi Xhi + Ahi Xlo + Alo Xhi on   */
                             /* BF16 MFMA with FP32 accumulation (the split scheme */
                             /* of Henry, Tang and Heinecke 2019): near-FP32       */
-                            /* accuracy at three BF16 contractions.  twa_run only,*/
-                            /* no two-time lags, dense pumps without decay        */
+                            /* accuracy at three BF16 contractions.  Runs (two-   */
+                            /* time lags included), batches, twa_tangent_w and    */
+                            /* twa_adjoint; dense pumps without decay matrix      */
 
 /* tile_config reported when the fused small-N kernel integrated the run */
 #define TWA_TILE_FUSED  99
@@ -371,8 +372,7 @@ typedef struct twa_batch_opts {
     int64_t burnin;          /* < 0: n_steps / 2                                  */
     double gamma;
     double s0z;
-    int32_t precision;       /* TWA_PREC_FP64 / FP32 / BF16 / FP16, or BF16X3    */
-                             /* (split BF16: n_lags must be 0)                   */
+    int32_t precision;       /* TWA_PREC_FP64 / FP32 / BF16 / FP16 / BF16X3     */
     int32_t use_graph;       /* capture the step loop in hipGraphs (default 1)   */
     int32_t steps_per_graph; /* steps captured per graph replay (<= 0: 16)       */
     const char* tune_cache;  /* autotuner cache file (NULL: no cache)            */

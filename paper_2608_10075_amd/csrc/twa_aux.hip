@@ -267,9 +267,11 @@ __global__ void seed_kernel(int64_t N, int64_t B, int64_t P, int64_t Bp, int64_t
         base[t] = cp == 0 ? one : S(0);
         base[SP + t] = cp == 1 ? one : S(0);
         base[2 * SP + t] = S(0);
-        typename Prec<PREC>::G* op = tXop + cp * C2 * P;
-        op[opcol(k, 0) * P + i] = Prec<PREC>::to_g(cp == 0 ? one : S(0));
-        op[opcol(k, 1) * P + i] = Prec<PREC>::to_g(cp == 1 ? one : S(0));
+        // operand columns of pitch P (split form: hi, lo, hi blocks of P)
+        constexpr int SPL = Prec<PREC>::SPLIT;
+        typename Prec<PREC>::G* op = tXop + cp * C2 * P * SPL;
+        put_op<PREC>(op + opcol(k, 0) * P * SPL + i, P, cp == 0 ? one : S(0));
+        put_op<PREC>(op + opcol(k, 1) * P * SPL + i, P, cp == 1 ? one : S(0));
     }
 }
 

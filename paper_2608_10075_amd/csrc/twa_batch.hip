@@ -531,10 +531,6 @@ int run_batch(const twa_point* pts, int np, const twa_batch_opts* o, twa_observa
         set_error("twa_run_batch: precision must be FP64, FP32, BF16, FP16 or split BF16");
         return TWA_EINVAL;
     }
-    if (o->precision == TWA_PREC_BF16X3 && o->n_lags > 0) {
-        set_error("twa_run_batch: the split-BF16 precision runs the forward step without lags (n_lags must be 0)");
-        return TWA_EINVAL;
-    }
     if (o->tile_config >= 0 && ((o->tile_config > 3 && o->tile_config != 7) ||
                                 (o->tile_config == 7 && o->precision == TWA_PREC_FP64))) {
         set_error("twa_run_batch: tile_config must be 0..3 or 7 (not 7 in FP64)");

@@ -107,8 +107,8 @@ int run_single(const twa_params* p, int64_t n_traj, double dt, int64_t n_steps, 
         set_error("twa_run: unknown precision");
         return TWA_EINVAL;
     }
-    if (p->precision == TWA_PREC_BF16X3 && (p->n_lags > 0 || (p->pump && p->pump->G))) {
-        set_error("twa_run: the split-BF16 precision runs the forward step without lags or decay matrix");
+    if (p->precision == TWA_PREC_BF16X3 && p->pump && p->pump->G) {
+        set_error("twa_run: the split-BF16 precision runs without a decay matrix");
         return TWA_EINVAL;
     }
     const twa_pump* pump = p->pump;

@@ -77,7 +77,7 @@ def test_batch_points_match_oracle(twa, prec, tile, tol):
         assert srel < tol and mrel < tol, (i, srel, mrel)
 
 
-@pytest.mark.parametrize("prec,tile,tol", [("fp64", -1, 1e-10), ("fp32", 7, 1e-5)])
+@pytest.mark.parametrize("prec,tile,tol", [("fp64", -1, 1e-10), ("fp32", 7, 1e-5), ("bf16x3", 7, 1e-4)])
 def test_batch_two_time_matches_oracle(twa, prec, tile, tol):
     """Two-time correlation of every point of the batch (response copies in
     grouped launches) against the oracle's block sums."""
@@ -132,7 +132,7 @@ def test_batch_rejects_bad_input(twa):
     with pytest.raises(twa.TWAError):
         twa.run_batch([(10, -1.0, 1.0, 1e-3, 0)], 8, 10)
     with pytest.raises(twa.TWAError):
-        twa.run_batch([(10, 1.0, 1.0, 1e-3, 0)], 8, 10, burnin=5, precision="bf16x3", n_lags=4)
+        twa.run_batch([(10, 1.0, 1.0, 1e-3, 0)], 8, 10, precision="bf16x3", tile_config=5)
     with pytest.raises(twa.TWAError):
         twa.run_batch([(10, 1.0, 1.0, 1e-3, 0)], 8, 10, tile_config=7, precision="fp64")
     with pytest.raises(twa.TWAError):

@@ -72,8 +72,8 @@ def test_split_bf16_headline_size_sampled(twa):
 def test_split_bf16_rejections(twa):
     p = twa.build_pump(64, 1.0, 1.0)
     with pytest.raises(twa.TWAError):
-        twa.run(p, 8, 1e-3, 20, precision="bf16x3", n_lags=4, norm_tol=-1)
-    with pytest.raises(twa.TWAError):
-        twa.run_batch([(64, 1.0, 1.0, 1e-3, 0)], 8, 20, burnin=10, precision="bf16x3", n_lags=4, norm_tol=-1)
-    with pytest.raises(twa.TWAError):
         twa.run(p, 8, 1e-3, 20, precision="bf16x3", pump_path="toeplitz", norm_tol=-1)
+    W = p.matrix("W")
+    model = twa.build_model(W, 0.5 * np.eye(64))
+    with pytest.raises(twa.TWAError):
+        twa.run(model, 8, 1e-3, 20, precision="bf16x3", norm_tol=-1)

@@ -41,6 +41,9 @@ TWO_TIME_CASES = [
     ("fp32", 8, 650, 130, 1e-5),
     ("fp32", 7, 1000, 64, 1e-5),
     ("fp32", 1, 100, 40, 1e-5),
+    # split BF16: 1e-4, the bound of its forward parity tests
+    ("bf16x3", 2, 300, 70, 1e-4),
+    ("bf16x3", 7, 650, 130, 1e-4),
 ]
 
 
