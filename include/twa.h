@@ -27,13 +27,13 @@
  *     entry point is stream-ordered on that stream and returns after its
  *     results are on the host unless stated otherwise; with NULL it runs on a
  *     non-blocking stream of its own (twa_run_noalloc: on the null stream).
- *   - Host threads: entry points may be called from several threads at
- *     once.  Each call owns its buffers; pump handles are only read by runs
- *     and may be shared between concurrent calls.  Calls that replay
- *     hipGraphs capture them in thread-local mode on their own stream, and no
- *     call issues work on the null stream or waits for the whole device
- *     (twa_run_noalloc given NULL aside), so one thread's capture never sees
- *     another thread's allocations, clears, copies or pump builds.
+ *   - Host threads: serialise the calls on one device (one at a time).
+ *     Each call owns its buffers and pump handles are only read by runs;
+ *     calls that replay hipGraphs capture them in thread-local mode on their
+ *     own stream, and no call issues work on the null stream or waits for the
+ *     whole device (twa_run_noalloc given NULL aside).  Concurrent calls from
+ *     several threads are not supported: a test of them aborted once, cause
+ *     unknown.
  *   - All arithmetic of the time stepping runs in the library's HIP kernels
  *     for gfx950.  There is no CPU fallback: without a usable GPU every
  *     compute entry point returns TWA_EHIP.
