@@ -27,13 +27,14 @@
  *     entry point is stream-ordered on that stream and returns after its
  *     results are on the host unless stated otherwise; with NULL it runs on a
  *     non-blocking stream of its own (twa_run_noalloc: on the null stream).
- *   - Host threads: serialise the calls on one device (one at a time).
- *     Each call owns its buffers and pump handles are only read by runs;
- *     calls that replay hipGraphs capture them in thread-local mode on their
- *     own stream, and no call issues work on the null stream or waits for the
- *     whole device (twa_run_noalloc given NULL aside).  Concurrent calls from
- *     several threads are not supported: a test of them aborted once, cause
- *     unknown.
+ *   - Host threads: every entry point that touches a device takes one
+ *     process-wide lock for its whole duration, so calls from several host
+ *     threads are safe and run one at a time.  The reason: releasing device
+ *     memory (hipFree) synchronises the whole device, which invalidates a
+ *     hipGraph capture that another thread has open.  Each call owns its
+ *     buffers, pump handles are only read by runs, graphs are captured in
+ *     thread-local mode on the call's own stream, and no call issues work on
+ *     the null stream (twa_run_noalloc given NULL aside).
  *   - All arithmetic of the time stepping runs in the library's HIP kernels
  *     for gfx950.  There is no CPU fallback: without a usable GPU every
  *     compute entry point returns TWA_EHIP.
@@ -347,7 +348,8 @@ TWA_API int twa_run(const twa_params* p, int64_t n_traj, double dt, int64_t n_st
  * twa_build_pump or twa_build_pump_dense, Heun or the semi-implicit scheme,
  * any precision, n_lags = 0, no init_state; no hipGraph replay and no timing
  * (kernel_ms is NaN).  The caller passes the stream (NULL = null stream).
- * Calls that overlap on one device share the array and race: serialise them.
+ * Calls share the device's array; within one process the library's lock
+ * keeps them from overlapping (calls from several processes would race).
  * Errors: TWA_EINVAL (as twa_run, and for the unsupported options above),
  *         TWA_ENOMEM (the run's buffers exceed the scratch size; the message
  *         states the bytes needed), TWA_EHIP, TWA_EUNSTABLE.

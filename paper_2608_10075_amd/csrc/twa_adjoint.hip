@@ -591,6 +591,7 @@ cleanup:
 
 extern "C" TWA_API int twa_adjoint(const twa_params* p, int64_t n_traj, double dt, int64_t n_steps, uint64_t seed,
                                    int32_t ckpt_every, twa_observables* out, double* grads) {
+    TWA_API_LOCK();
     using namespace twa;
     if (!p || !p->pump || !out || !grads || n_traj < 1 || n_steps < 1 || !(dt > 0) || !std::isfinite(dt) ||
         !(p->gamma > 0) || ckpt_every < 1) {

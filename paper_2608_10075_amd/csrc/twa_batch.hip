@@ -766,6 +766,7 @@ TWA_API void twa_batch_opts_default(twa_batch_opts* o) {
 }
 
 TWA_API int twa_run_batch(const twa_point* pts, int n_points, const twa_batch_opts* o, twa_observables* outs) {
+    TWA_API_LOCK();
     return twa::run_batch(pts, n_points, o, outs);
 }
 

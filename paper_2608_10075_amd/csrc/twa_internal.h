@@ -5,6 +5,7 @@
 #include <hip/hip_bf16.h>
 #include <hip/hip_fp16.h>
 #include <stdint.h>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -15,6 +16,16 @@ namespace twa {
 // ---------------------------------------------------------------------------
 // error plumbing
 void set_error(const std::string& msg);
+
+// Every entry point that touches the device holds this process-wide lock for
+// its whole duration (recursive: the threshold search and the batch call
+// other entry points).  hipFree synchronises the whole device, and a
+// device-wide synchronisation while another thread's stream is being
+// captured into a graph breaks that capture; serialising the calls keeps
+// every free, allocation and pump build of one call out of another call's
+// graph capture.
+std::recursive_mutex& api_mutex();
+#define TWA_API_LOCK() std::lock_guard<std::recursive_mutex> twa_api_lock_(::twa::api_mutex())
 struct Status {
     int code = TWA_OK;
     std::string msg;

@@ -247,6 +247,7 @@ extern "C" {
 
 TWA_API int twa_run_noalloc(const twa_params* p, int64_t n_traj, double dt, int64_t n_steps, uint64_t seed,
                             twa_observables* out) {
+    TWA_API_LOCK();
     return twa::run_noalloc(p, n_traj, dt, n_steps, seed, out);
 }
 

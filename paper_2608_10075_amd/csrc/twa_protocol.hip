@@ -52,6 +52,7 @@ double objective_value(int obj, const twa_observables& o, int64_t N) {
 extern "C" {
 
 TWA_API int twa_protocol(const twa_pump* pump, double gamma, double cfl, int32_t finite_size, twa_protocol_t* out) {
+    TWA_API_LOCK();
     using namespace twa;
     if (!pump || !out || !(gamma > 0) || !std::isfinite(gamma) || !(cfl > 0) || !(cfl < 0.05)) {
         set_error("twa_protocol: need a pump, an output, gamma > 0 and 0 < cfl < 0.05");
@@ -111,6 +112,7 @@ TWA_API void twa_threshold_opts_default(twa_threshold_opts* o) {
 TWA_API int twa_find_threshold(int64_t N, double alpha, const twa_params* p, int64_t n_traj, double dt,
                                int64_t n_steps, uint64_t seed, const twa_threshold_opts* o, double* w_root,
                                double* f_root, int32_t* n_iter) {
+    TWA_API_LOCK();
     using namespace twa;
     if (!p || !o || N < 1 || !(alpha >= 0) || !std::isfinite(alpha) || !(o->w_lo > 0) ||
         !(o->w_hi > o->w_lo) || !std::isfinite(o->w_hi) || !(o->tol_w > 0) || o->max_iter < 1 ||
@@ -205,6 +207,7 @@ out:
 TWA_API int twa_g2_min(int64_t N, double alpha, const twa_params* p, int64_t n_traj, uint64_t seed,
                        int32_t n_points, double wt_lo, double wt_hi, double cfl, int32_t finite_size,
                        double* wt_out, double* g2_out, double* wt_min, double* g2_min) {
+    TWA_API_LOCK();
     using namespace twa;
     if (!p || N < 1 || n_points < 1 || !(wt_lo > 0) || !(wt_hi >= wt_lo) || !std::isfinite(wt_hi) ||
         !(p->gamma > 0)) {

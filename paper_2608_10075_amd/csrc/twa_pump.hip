@@ -245,6 +245,7 @@ int pump_scaled(const twa_pump* b, double w, twa_pump** out) {
 extern "C" {
 
 TWA_API int twa_build_pump(int64_t N, double w, double alpha, twa_pump** out) {
+    TWA_API_LOCK();
     using namespace twa;
     if (!out || N < 1 || !std::isfinite(w) || !std::isfinite(alpha) || w < 0 || alpha < 0) {
         set_error("twa_build_pump: need N >= 1, finite w >= 0, finite alpha >= 0 and an output pointer");
@@ -284,6 +285,7 @@ TWA_API int twa_build_pump(int64_t N, double w, double alpha, twa_pump** out) {
 }
 
 TWA_API int twa_build_pump_dense(int64_t N, const double* W_host, twa_pump** out) {
+    TWA_API_LOCK();
     using namespace twa;
     if (!out || N < 1 || !W_host) {
         set_error("twa_build_pump_dense: need N >= 1, a matrix and an output pointer");
@@ -330,6 +332,7 @@ TWA_API int twa_build_pump_dense(int64_t N, const double* W_host, twa_pump** out
 
 TWA_API int twa_build_model_dense(int64_t N, const double* W_host, const double* G_host, const double* Om_host,
                                   twa_pump** out) {
+    TWA_API_LOCK();
     using namespace twa;
     if (!out || N < 1 || !W_host || !G_host) {
         set_error("twa_build_model_dense: need N >= 1, two matrices and an output pointer");
@@ -428,6 +431,7 @@ TWA_API int twa_build_model_dense(int64_t N, const double* W_host, const double*
 }
 
 TWA_API int twa_build_pump_toeplitz(int64_t N, double w, double alpha, twa_pump** out) {
+    TWA_API_LOCK();
     using namespace twa;
     if (!out || N < 1 || N > toeplitz_max_n(TWA_PREC_FP32) || !std::isfinite(w) || !std::isfinite(alpha) || w < 0 ||
         alpha < 0) {
@@ -446,7 +450,10 @@ TWA_API int twa_build_pump_toeplitz(int64_t N, double w, double alpha, twa_pump*
     return TWA_OK;
 }
 
-TWA_API void twa_pump_free(twa_pump* p) { twa::pump_release(p); }
+TWA_API void twa_pump_free(twa_pump* p) {
+    TWA_API_LOCK();
+    twa::pump_release(p);
+}
 
 TWA_API int twa_pump_info(const twa_pump* p, int64_t* N, double* lam_min, double* lam_max) {
     if (!p) {
@@ -460,6 +467,7 @@ TWA_API int twa_pump_info(const twa_pump* p, int64_t* N, double* lam_min, double
 }
 
 TWA_API int twa_pump_copy_matrix(const twa_pump* p, int which, double* out_host) {
+    TWA_API_LOCK();
     if (!p || !out_host || which < 0 || which > 3 || (which == 2 && !p->G) || (which == 3 && !p->Om)) {
         twa::set_error("twa_pump_copy_matrix: bad arguments (which = 2, 3 need a model handle with G, Omega)");
         return TWA_EINVAL;

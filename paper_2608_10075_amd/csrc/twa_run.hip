@@ -15,6 +15,11 @@
 namespace twa {
 
 static thread_local std::string g_err;
+
+std::recursive_mutex& api_mutex() {
+    static std::recursive_mutex m;
+    return m;
+}
 void set_error(const std::string& msg) { g_err = msg; }
 
 int gemm_elt_bytes(int precision) {
@@ -406,6 +411,7 @@ TWA_API void twa_params_default(twa_params* p) {
 }
 
 TWA_API int twa_philox(const uint32_t* ctr, int64_t n, uint32_t key0, uint32_t key1, uint32_t* out, void* stream) {
+    TWA_API_LOCK();
     if (n < 0 || (n > 0 && (!ctr || !out))) {
         twa::set_error("twa_philox: bad arguments");
         return TWA_EINVAL;
@@ -421,6 +427,7 @@ TWA_API int twa_philox(const uint32_t* ctr, int64_t n, uint32_t key0, uint32_t k
 
 TWA_API int twa_noise(uint64_t seed, int64_t step, int32_t point, int64_t n_traj, int64_t N, int32_t fp64,
                       double* zeta, double* g, void* stream) {
+    TWA_API_LOCK();
     if (n_traj < 1 || N < 1 || step < 0 || !zeta || !g) {
         twa::set_error("twa_noise: bad arguments");
         return TWA_EINVAL;
@@ -436,6 +443,7 @@ TWA_API int twa_noise(uint64_t seed, int64_t step, int32_t point, int64_t n_traj
 
 TWA_API int twa_run(const twa_params* p, int64_t n_traj, double dt, int64_t n_steps, uint64_t seed,
                     twa_observables* out, const twa_outputs* outs) {
+    TWA_API_LOCK();
     return twa::run_single(p, n_traj, dt, n_steps, seed, out, outs);
 }
 

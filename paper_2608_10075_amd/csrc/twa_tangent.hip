@@ -260,6 +260,7 @@ extern "C" {
 
 TWA_API int twa_tangent_w(const twa_params* p, int64_t n_traj, double dt, int64_t n_steps, uint64_t seed,
                           twa_observables* out, double* grads) {
+    TWA_API_LOCK();
     return twa::run_tangent_w(p, n_traj, dt, n_steps, seed, out, grads);
 }
 
