@@ -1,0 +1,268 @@
+"""Planted mistakes in the oracle (CPU only).
+
+Each case replaces one oracle function or constant with a plausible wrong
+variant (a dropped term, a flipped sign, a slipped index, a wrong scale or
+weight) for the duration of one test, and requires that at least one of the
+named pins from tests/test_oracle_*.py then fails.  pytest's monkeypatch
+restores the oracle afterwards, so nothing here changes what other tests see.
+The variants below are written to differ from the oracle in exactly the one
+planted place: ``test_unplanted_variants_equal_the_oracle`` checks that each
+variant with no mistake planted reproduces the oracle bit for bit.
+"""
+import dataclasses
+import os
+
+import numpy as np
+import pytest
+
+from oracle import grad as ograd
+from oracle import observables, philox, pump, twa
+from tests import test_oracle_dynamics as dyn
+from tests import test_oracle_grad as tgrad
+from tests import test_oracle_pump as tpump
+from tests import test_oracle_rng as trng
+from tests import test_oracle_sib as tsib
+from tests import test_oracle_stationary as tstat
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+# ---- variants of the oracle's functions, each with one switchable mistake
+
+def _increment(flip_pump=False, drop_collective=False, flip_z=False, y_field_from_x=False):
+    """Eq. (S1) increment (no coherent exchange)."""
+    def increment(state, W, gamma, dt, dxi, dchi):
+        x, y, z = state
+        Sx = x.sum(axis=1)[:, None]
+        Sy = y.sum(axis=1)[:, None]
+        c = 0.0 if drop_collective else 0.5 * gamma
+        sgn = 0.5 if flip_pump else -0.5
+        hx = (c * Sx + sgn * twa._matvec(W, x)) * dt + dxi[0][:, None] - dchi[0]
+        hy = (c * Sy + sgn * twa._matvec(W, x if y_field_from_x else y)) * dt + dxi[1][:, None] - dchi[1]
+        dz = (x * hx + y * hy) if flip_z else -(x * hx + y * hy)
+        return z * hx, z * hy, dz, (hx, hy)
+    return increment
+
+
+def _noise_increments(drop_gamma=False, dt_for_sqrt_dt=False, same_pump_noise_xy=False):
+    """Noise increments of one step for a dense pump."""
+    def noise_increments(cfg, p, step):
+        n, B = cfg.n_spin, cfg.n_traj
+        gx, gy = philox.collective_noise(cfg.seed, step, B, cfg.point, cfg.traj)
+        sg = np.sqrt(cfg.dt) if drop_gamma else np.sqrt(cfg.gamma * cfg.dt)
+        sq = cfg.dt if dt_for_sqrt_dt else np.sqrt(cfg.dt)
+        zx, zy = philox.pump_noise(cfg.seed, step, B, n, cfg.point, cfg.traj)
+        if same_pump_noise_xy:
+            zy = zx
+        return (sg * gx, sg * gy), (sq * (zx @ p.F.T), sq * (zy @ p.F.T))
+    return noise_increments
+
+
+def _heun_step(corrector="trapezoid"):
+    """Stochastic Heun step; the corrector is the trapezoid s + (D(s) + D(s~))/2."""
+    def heun_step(state, W, gamma, dt, dxi, dchi):
+        d1 = twa.increment(state, W, gamma, dt, dxi, dchi)
+        pred = tuple(s + d for s, d in zip(state, d1[:3]))
+        d2 = twa.increment(pred, W, gamma, dt, dxi, dchi)
+        if corrector == "trapezoid":
+            new = tuple(s + 0.5 * (a + b) for s, a, b in zip(state, d1[:3], d2[:3]))
+        elif corrector == "sum":          # weights 1, 1 instead of 1/2, 1/2
+            new = tuple(s + a + b for s, a, b in zip(state, d1[:3], d2[:3]))
+        else:                             # the predictor alone (Euler)
+            new = pred
+        return new, (d1, pred, d2)
+    return heun_step
+
+
+def _sib_step(second_field_at="midpoint"):
+    """Semi-implicit step; the second stage takes the field at (s_n + s~)/2."""
+    def sib_step(state, W, gamma, dt, dxi, dchi):
+        hx, hy = twa.fields(state, W, gamma, dt, dxi, dchi)
+        pred = twa.midpoint_rotation(state, hx, hy)
+        at = tuple(0.5 * (a + b) for a, b in zip(state, pred)) if second_field_at == "midpoint" else pred
+        hx2, hy2 = twa.fields(at, W, gamma, dt, dxi, dchi)
+        return twa.midpoint_rotation(state, hx2, hy2), pred
+    return sib_step
+
+
+def _derived(drop_half_z=False, c_t3=2.0, drop_z_third=False, c_zz=0.5, c_t2=4.0 / 3.0):
+    """(Sz, <S+S->, g2) from the moments (SM Sec. S1 step 6, Eq. (S2))."""
+    def derived(m):
+        T2, T3, T4, Z, ZZ = m
+        spsm = T2 if drop_half_z else T2 + 0.5 * Z
+        zterm = 0.0 if drop_z_third else Z / 3.0
+        num = T4 + c_t3 * T3 - zterm + c_zz * ZZ - c_t2 * T2
+        with np.errstate(divide="ignore", invalid="ignore"):
+            return Z, spsm, num / (spsm * spsm)
+    return derived
+
+
+def _moments(t2_scale=0.25):
+    def moments(state):
+        Sx, Sy, Sz = twa.collective_sums(*state)
+        T2 = t2_scale * (Sx * Sx + Sy * Sy)
+        return np.stack([T2, T2 * Sz, T2 * T2, Sz, Sz * Sz], axis=1)
+    return moments
+
+
+def _pump_matrix(flip_exponent=False):
+    def pump_matrix(n_spin, w, alpha):
+        i = np.arange(n_spin)
+        d = np.abs(i[:, None] - i[None, :]).astype(np.float64)
+        return w * (d + 1.0) ** alpha if flip_exponent else w / (d + 1.0) ** alpha
+    return pump_matrix
+
+
+def _box_muller(drop_two=False):
+    def box_muller(a, b):
+        a = np.asarray(a, dtype=np.uint64)
+        b = np.asarray(b, dtype=np.uint64)
+        u1 = ((a >> np.uint64(8)) + np.uint64(1)).astype(np.float64) * 2.0 ** -24
+        u2 = (b >> np.uint64(8)).astype(np.float64) * 2.0 ** -24
+        r = np.sqrt(-np.log(u1)) if drop_two else np.sqrt(-2.0 * np.log(u1))
+        return r * np.cos(2.0 * np.pi * u2), r * np.sin(2.0 * np.pi * u2)
+    return box_muller
+
+
+# ---- the planted mistakes and the pins that must notice each one
+
+_REAL_BUILD_PUMP = pump.build_pump
+_REAL_FINALIZE = observables.finalize
+_REAL_DPUMP = pump.dpump_dalpha
+
+
+def _build_pump_factor_is_w(n_spin, w, alpha):
+    p = _REAL_BUILD_PUMP(n_spin, w, alpha)
+    return dataclasses.replace(p, F=p.W.copy())
+
+
+def _finalize_without_jackknife_factor(traj_moments):
+    out = _REAL_FINALIZE(traj_moments)
+    J = min(32, traj_moments.shape[0])
+    for k in list(out):
+        if k.endswith("_se"):
+            out[k] *= np.sqrt(J / (J - 1.0))
+    return out
+
+
+CASES = {
+    "pump drift with the wrong sign": (
+        [(twa, "increment", _increment(flip_pump=True))],
+        [lambda: dyn.test_sz_rate_at_t0_matches_lindblad(2, True), dyn.test_noiseless_correlated_pump_vs_dop853]),
+    "collective drift Gamma S/2 dropped": (
+        [(twa, "increment", _increment(drop_collective=True))],
+        [dyn.test_noiseless_collective_decay_closed_form_second_order,
+         lambda: dyn.test_sz_rate_at_t0_matches_lindblad(2, True)]),
+    "ds^z with the wrong sign": (
+        [(twa, "increment", _increment(flip_z=True))],
+        [dyn.test_increment_orthogonal_to_spin]),
+    "y field built from s^x (index slip)": (
+        [(twa, "increment", _increment(y_field_from_x=True))],
+        [dyn.test_noiseless_correlated_pump_vs_dop853]),
+    "collective noise without Gamma": (
+        [(twa, "noise_increments", _noise_increments(drop_gamma=True))],
+        [tstat.test_noise_increments_follow_the_noise_law_of_eq_s1]),
+    "pump noise scaled by dt instead of sqrt(dt)": (
+        [(twa, "noise_increments", _noise_increments(dt_for_sqrt_dt=True))],
+        [tstat.test_noise_increments_follow_the_noise_law_of_eq_s1]),
+    "one pump noise for both x and y": (
+        [(twa, "noise_increments", _noise_increments(same_pump_noise_xy=True))],
+        [tstat.test_noise_increments_follow_the_noise_law_of_eq_s1]),
+    "Heun corrector weights 1, 1": (
+        [(twa, "heun_step", _heun_step("sum"))],
+        [dyn.test_heun_norm_error_is_second_order_per_step,
+         dyn.test_noiseless_collective_decay_closed_form_second_order]),
+    "Heun corrector dropped (Euler)": (
+        [(twa, "heun_step", _heun_step("euler"))],
+        [dyn.test_noiseless_collective_decay_closed_form_second_order]),
+    "midpoint rotation about +b": (
+        [(twa, "midpoint_rotation", lambda st, hx, hy, f=twa.midpoint_rotation: f(st, -hx, -hy))],
+        [tsib.test_midpoint_stage_is_the_rotation_about_minus_b,
+         tsib.test_sib_noiseless_collective_decay_closed_form_second_order]),
+    "semi-implicit second field at the predictor": (
+        [(twa, "sib_step", _sib_step("predictor"))],
+        [tsib.test_sib_noiseless_collective_decay_closed_form_second_order,
+         tsib.test_sib_noiseless_correlated_pump_vs_dop853]),
+    "<S+S-> without the S^z/2 ordering term": (
+        [(observables, "derived", _derived(drop_half_z=True))],
+        [lambda: dyn.test_initial_moments_exact_enumeration(2), dyn.test_sampled_initial_state,
+         lambda: tstat.test_eq_s2_is_an_exact_operator_identity(3)]),
+    "g2 numerator with -2 T3": (
+        [(observables, "derived", _derived(c_t3=-2.0))],
+        [lambda: tstat.test_alpha0_w_equals_gamma_g2_tends_to_paper_six_fifths(GOLDEN),
+         lambda: tstat.test_eq_s2_is_an_exact_operator_identity(3)]),
+    "g2 numerator without -S^z/3": (
+        [(observables, "derived", _derived(drop_z_third=True))],
+        [lambda: tstat.test_eq_s2_is_an_exact_operator_identity(3)]),
+    "g2 numerator with ZZ instead of ZZ/2": (
+        [(observables, "derived", _derived(c_zz=1.0))],
+        [lambda: tstat.test_alpha0_w_equals_gamma_g2_tends_to_paper_six_fifths(GOLDEN),
+         lambda: tstat.test_eq_s2_is_an_exact_operator_identity(3)]),
+    "g2 numerator with -2/3 T2 instead of -4/3 T2": (
+        [(observables, "derived", _derived(c_t2=2.0 / 3.0))],
+        [lambda: tstat.test_alpha0_w_equals_gamma_g2_tends_to_paper_six_fifths(GOLDEN),
+         lambda: tstat.test_eq_s2_is_an_exact_operator_identity(3)]),
+    "T2 = |S|^2 / 2 instead of / 4": (
+        [(twa, "moments", _moments(0.5))],
+        [lambda: dyn.test_initial_moments_exact_enumeration(2)]),
+    "Eq. (2) exponent with the wrong sign": (
+        [(pump, "pump_matrix", _pump_matrix(flip_exponent=True))],
+        [tpump.test_matrix_entries_eq2]),
+    "noise factor F = W instead of its square root": (
+        [(pump, "build_pump", _build_pump_factor_is_w), (twa, "build_pump", _build_pump_factor_is_w)],
+        [lambda: tpump.test_factor_squares_to_w(33, 2.0, 0.5), tstat.test_pump_noise_covariance_equals_w]),
+    "Box-Muller radius without the factor 2": (
+        [(philox, "box_muller", _box_muller(drop_two=True))],
+        [trng.test_box_muller_moments_and_ks]),
+    "Philox Weyl increment off by one bit": (
+        [(philox, "PHILOX_W1", np.uint64(0xBB67AE84))],
+        [lambda: trng.test_philox_known_answers(GOLDEN)]),
+    "jackknife without the (J-1)/J factor": (
+        [(observables, "finalize", _finalize_without_jackknife_factor)],
+        [tstat.test_jackknife_se_of_mean_matches_block_standard_error]),
+    "d w_ij / d alpha with the wrong sign": (
+        [(ograd, "dpump_dalpha", lambda n, w, a: -_REAL_DPUMP(n, w, a))],
+        [tgrad.test_pathwise_gradient_matches_central_differences]),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_planted_mistake_fails_a_pin(name, monkeypatch):
+    patches, pins = CASES[name]
+    for mod, attr, value in patches:
+        monkeypatch.setattr(mod, attr, value)
+    failed = []
+    for pin in pins:
+        try:
+            pin()
+        except AssertionError:
+            failed.append(getattr(pin, "__name__", "pin"))
+    assert failed, "no pin noticed the planted mistake: %s" % name
+
+
+def test_unplanted_variants_equal_the_oracle():
+    """The variants above with no mistake switched on are the oracle itself."""
+    rng = np.random.default_rng(5)
+    n, B, gamma, dt = 6, 4, 0.7, 1e-2
+    p = pump.build_pump(n, 1.3, 0.9)
+    st = tuple(rng.standard_normal((B, n)) for _ in range(3))
+    dxi = (rng.standard_normal(B), rng.standard_normal(B))
+    dchi = (rng.standard_normal((B, n)), rng.standard_normal((B, n)))
+    for a, b in zip(_increment()(st, p.W, gamma, dt, dxi, dchi)[:3], twa.increment(st, p.W, gamma, dt, dxi, dchi)[:3]):
+        assert np.array_equal(a, b)
+    for a, b in zip(_heun_step()(st, p.W, gamma, dt, dxi, dchi)[0], twa.heun_step(st, p.W, gamma, dt, dxi, dchi)[0]):
+        assert np.array_equal(a, b)
+    for a, b in zip(_sib_step()(st, p.W, gamma, dt, dxi, dchi)[0], twa.sib_step(st, p.W, gamma, dt, dxi, dchi)[0]):
+        assert np.array_equal(a, b)
+    cfg = twa.RunConfig(n_spin=n, w=1.3, alpha=0.9, n_traj=B, dt=dt, n_steps=1, gamma=gamma, seed=3)
+    for u, v in zip(_noise_increments()(cfg, p, 7), twa.noise_increments(cfg, p, 7)):
+        for a, b in zip(u, v):
+            assert np.array_equal(a, b)
+    m = rng.standard_normal((5, 9))
+    for a, b in zip(_derived()(m), observables.derived(m)):
+        assert np.array_equal(a, b)
+    assert np.array_equal(_moments()(st), twa.moments(st))
+    assert np.array_equal(_pump_matrix()(9, 1.3, 0.9), pump.pump_matrix(9, 1.3, 0.9))
+    words = philox.philox4x32_10(np.arange(64, dtype=np.uint64), 1, 2, 3, 4, 5)
+    for a, b in zip(_box_muller()(words[0], words[1]), philox.box_muller(words[0], words[1])):
+        assert np.array_equal(a, b)

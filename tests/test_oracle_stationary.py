@@ -27,6 +27,80 @@ def test_pump_noise_covariance_equals_w():
     assert abs(g.var() - 1.0) < 4.5 * np.sqrt(2.0 / g.size)
 
 
+def test_noise_increments_follow_the_noise_law_of_eq_s1():
+    """The increments the integrator is driven with, at Gamma != 1 and a small
+    dt: <dxi^a dxi^b> = Gamma dt delta_ab, <dchi^a_i dchi^b_j> = w_ij dt delta_ab,
+    and no correlation between the collective and the pump noise (Eq. (S1))."""
+    n, B, gamma, dt, w, alpha = 5, 4000, 0.37, 2.5e-3, 1.7, 0.8
+    p = pump.build_pump(n, w, alpha)
+    cfg = twa.RunConfig(n_spin=n, w=w, alpha=alpha, n_traj=B, dt=dt, n_steps=1, gamma=gamma, seed=13)
+    xi, chi = [], []
+    for step in range(40):
+        dxi, dchi = twa.noise_increments(cfg, p, step)
+        xi.append(np.stack(dxi, axis=1))
+        chi.append(np.concatenate(dchi, axis=1))
+    X, C = np.concatenate(xi), np.concatenate(chi)
+    M = X.shape[0]
+    cx = X.T @ X / M                       # (2, 2)
+    assert abs(cx[0, 0] / (gamma * dt) - 1) < 4.5 * np.sqrt(2.0 / M)
+    assert abs(cx[1, 1] / (gamma * dt) - 1) < 4.5 * np.sqrt(2.0 / M)
+    assert abs(cx[0, 1] / (gamma * dt)) < 4.5 / np.sqrt(M)
+    cc = C.T @ C / M / dt                  # (2n, 2n): blocks xx, xy / yx, yy
+    d = np.diag(p.W)
+    se_same = np.sqrt((np.outer(d, d) + p.W ** 2) / M)
+    se_cross = np.sqrt(np.outer(d, d) / M)
+    assert np.all(np.abs(cc[:n, :n] - p.W) < 4.5 * se_same)
+    assert np.all(np.abs(cc[n:, n:] - p.W) < 4.5 * se_same)
+    assert np.all(np.abs(cc[:n, n:]) < 4.5 * se_cross)
+    xc = X.T @ C / M / dt                  # (2, 2n)
+    assert np.all(np.abs(xc) < 4.5 * np.sqrt(gamma * np.concatenate([d, d])[None, :] / M))
+
+
+def _weyl(ops):
+    """Fully symmetrised product of operators: the operator whose expectation
+    the TWA average of the corresponding classical product is."""
+    import itertools
+    import math
+    acc = np.zeros_like(ops[0])
+    for perm in itertools.permutations(range(len(ops))):
+        m = np.eye(ops[0].shape[0], dtype=ops[0].dtype)
+        for j in perm:
+            m = m @ ops[j]
+        acc += m
+    return acc / math.factorial(len(ops))
+
+
+@pytest.mark.parametrize("n", [2, 3, 4])
+def test_eq_s2_is_an_exact_operator_identity(n):
+    """SM Sec. S1 step 6 and Eq. (S2): with the TWA moments T2 = |S+|^2,
+    T3 = T2 S^z, T4 = T2^2, Z = S^z, ZZ = (S^z)^2 replaced by the exact
+    expectations of the Weyl-ordered collective operators in a random mixed
+    state, ``observables.derived`` returns the exact normal-ordered <S+S->
+    and <S+S+S-S-> / <S+S->^2 (every coefficient of Eq. (S2) enters)."""
+    ops = lindblad.operators(n)           # (sigma+, sigma-, sigma^z) per site
+    Sp, Sm, Sz = sum(ops[0]), sum(ops[1]), sum(ops[2])
+    Sx, Sy = Sp + Sm, -1j * (Sp - Sm)
+    rng = np.random.default_rng(40 + n)
+    d = 2 ** n
+    R = rng.normal(size=(d, d)) + 1j * rng.normal(size=(d, d))
+    rho = R @ R.conj().T
+    rho /= np.trace(rho)
+
+    def ev(op):
+        return np.trace(rho @ op).real
+
+    T2 = 0.25 * (ev(_weyl([Sx, Sx])) + ev(_weyl([Sy, Sy])))
+    T3 = 0.25 * (ev(_weyl([Sx, Sx, Sz])) + ev(_weyl([Sy, Sy, Sz])))
+    T4 = (ev(_weyl([Sx] * 4)) + 2 * ev(_weyl([Sx, Sx, Sy, Sy])) + ev(_weyl([Sy] * 4))) / 16.0
+    Z, ZZ = ev(Sz), ev(Sz @ Sz)
+    _, spsm, g2 = observables.derived(np.array([T2, T3, T4, Z, ZZ]))
+    exact2 = ev(Sp @ Sm)
+    exact4 = ev(Sp @ Sp @ Sm @ Sm)
+    assert abs(spsm - exact2) < 1e-12 * max(1.0, abs(exact2))
+    assert abs(g2 * spsm * spsm - exact4) < 1e-11 * max(1.0, abs(exact4))
+    assert abs(T3) > 1e-3              # the state exercises every moment
+
+
 def test_lindblad_collective_steady_state_is_detailed_balance():
     """Brute-force Eq. (1) at alpha = 0 from the all-up state relaxes to the
     detailed-balance populations quoted in the SM (collective pump)."""
