@@ -15,14 +15,18 @@ import os
 import numpy as np
 import pytest
 
+from oracle import decay as odecay
 from oracle import grad as ograd
-from oracle import observables, philox, pump, twa
+from oracle import observables, philox, protocol, pump, toeplitz, twa
+from tests import test_oracle_decay as tdecay
 from tests import test_oracle_dynamics as dyn
 from tests import test_oracle_grad as tgrad
+from tests import test_oracle_protocol as tproto
 from tests import test_oracle_pump as tpump
 from tests import test_oracle_rng as trng
 from tests import test_oracle_sib as tsib
 from tests import test_oracle_stationary as tstat
+from tests import test_oracle_toeplitz as ttoep
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
@@ -124,6 +128,95 @@ def _box_muller(drop_two=False):
     return box_muller
 
 
+def _increment_tangent(drop_dz_h=False):
+    """Directional derivative of the increment at fixed noise."""
+    def increment_tangent(state, dstate, fields, W, gamma, dt):
+        x, y, z = state
+        dx, dy, dz = dstate
+        hx, hy = fields
+        dhx = (0.5 * gamma * dx.sum(axis=1)[:, None] - 0.5 * twa._matvec(W, dx)) * dt
+        dhy = (0.5 * gamma * dy.sum(axis=1)[:, None] - 0.5 * twa._matvec(W, dy)) * dt
+        if drop_dz_h:
+            return z * dhx, z * dhy, -(dx * hx + x * dhx + dy * hy + y * dhy)
+        return (dz * hx + z * dhx,
+                dz * hy + z * dhy,
+                -(dx * hx + x * dhx + dy * hy + y * dhy))
+    return increment_tangent
+
+
+def _incr_vjp(flip_collective=False, w_transposed=False):
+    """Transpose of the increment's linearisation (reverse mode)."""
+    def incr_vjp(state, mu, fields_dt, W, gamma, dt):
+        x, y, z = state
+        hx, hy = fields_dt
+        ux, uy, uz = mu
+        cx = -uz * hx
+        cy = -uz * hy
+        cz = ux * hx + uy * hy
+        nx = ux * z - uz * x
+        ny = uy * z - uz * y
+        g = -0.5 * gamma if flip_collective else 0.5 * gamma
+        Wm = W.T if w_transposed else W
+        cx = cx + (g * nx.sum(axis=1)[:, None] - 0.5 * (nx @ Wm)) * dt
+        cy = cy + (g * ny.sum(axis=1)[:, None] - 0.5 * (ny @ Wm)) * dt
+        return cx, cy, cz
+    return incr_vjp
+
+
+def _first_column(mirror_off_by_one=False):
+    def first_column(n_spin, w, alpha, M=None):
+        M = toeplitz.embedding_size(n_spin) if M is None else M
+        j = np.arange(M)
+        d = np.minimum(j, M - 1 - j if mirror_off_by_one else M - j).astype(np.float64)
+        return w / (1.0 + d) ** alpha
+    return first_column
+
+
+def _decay_derived(r_sign=-1.0):
+    """(intensity, g2) of correlated emission from the nine quantities."""
+    def derived(m):
+        E2, E2E2, E2D, Q3, R, DD, U, V, D = m
+        inten = E2 + 0.5 * D
+        num = E2E2 + E2D + Q3 + r_sign * (R / 3.0) + 0.25 * (DD + U) - (4.0 / 3.0) * V
+        with np.errstate(divide="ignore", invalid="ignore"):
+            return inten, num / (inten * inten)
+    return derived
+
+
+def _spectrum(factor=2.0):
+    def spectrum(corr, tau, pad=8):
+        L = corr.shape[0]
+        n = pad * L
+        c = np.zeros(n, dtype=np.complex128)
+        c[:L] = corr
+        c[0] *= 0.5
+        c[L - 1] *= 0.5
+        s = n * np.fft.ifft(c)
+        omega = 2.0 * np.pi * np.fft.fftfreq(n, d=tau)
+        S = factor * tau * s.real
+        order = np.argsort(omega)
+        return omega[order], S[order]
+    return spectrum
+
+
+_REAL_PROTOCOL = protocol.protocol
+
+
+def _protocol_without_gamma_n(N, w, alpha, gamma=1.0, cfl=0.04, finite_size=False, pump=None):
+    pr = _REAL_PROTOCOL(N, w, alpha, gamma, cfl, finite_size, pump)
+    dt = cfl / pr.lam_max
+    return dataclasses.replace(pr, dt=dt, n_prep=int(np.ceil(pr.tau_s / dt - 1e-9)),
+                               n_window=int(np.ceil(pr.tau / dt - 1e-9)))
+
+
+def _quarter(omega, S):
+    """Full width at a quarter of the maximum (the planted mistake)."""
+    k = int(np.argmax(S))
+    level = 0.25 * S[k]
+    above = np.nonzero(S > level)[0]
+    return float(omega[above[-1]] - omega[above[0]])
+
+
 # ---- the planted mistakes and the pins that must notice each one
 
 _REAL_BUILD_PUMP = pump.build_pump
@@ -220,6 +313,30 @@ CASES = {
     "jackknife without the (J-1)/J factor": (
         [(observables, "finalize", _finalize_without_jackknife_factor)],
         [tstat.test_jackknife_se_of_mean_matches_block_standard_error]),
+    "tangent increment without dz h": (
+        [(twa, "increment_tangent", _increment_tangent(drop_dz_h=True))],
+        [tstat.test_response_fd_matches_tangent, tgrad.test_heun_vjp_is_the_transpose_of_the_tangent_step]),
+    "reverse-mode collective term with the wrong sign": (
+        [(ograd, "_incr_vjp", _incr_vjp(flip_collective=True))],
+        [tgrad.test_heun_vjp_is_the_transpose_of_the_tangent_step]),
+    "reverse-mode product with W instead of its transpose": (
+        [(ograd, "_incr_vjp", _incr_vjp(w_transposed=True))],
+        [tgrad.test_heun_vjp_is_the_transpose_of_the_tangent_step]),
+    "circulant embedding mirrored at M - 1 - j": (
+        [(toeplitz, "first_column", _first_column(mirror_off_by_one=True))],
+        [lambda: ttoep.test_embedding_block_spectrum_and_drift(7, 1.0)]),
+    "correlated-decay estimator with +R/3": (
+        [(odecay, "derived", _decay_derived(r_sign=1.0))],
+        [lambda: tdecay.test_estimator_is_an_exact_operator_identity(3, "random")]),
+    "step criterion without Gamma N": (
+        [(protocol, "protocol", _protocol_without_gamma_n)],
+        [tproto.test_step_criterion_and_times]),
+    "spectrum without the factor 2": (
+        [(observables, "spectrum", _spectrum(factor=1.0))],
+        [tstat.test_spectrum_of_exponential_has_fwhm_two_gamma]),
+    "linewidth taken at a quarter of the maximum": (
+        [(observables, "fwhm", _quarter)],
+        [tstat.test_spectrum_of_exponential_has_fwhm_two_gamma]),
     "d w_ij / d alpha with the wrong sign": (
         [(ograd, "dpump_dalpha", lambda n, w, a: -_REAL_DPUMP(n, w, a))],
         [tgrad.test_pathwise_gradient_matches_central_differences]),
@@ -263,6 +380,20 @@ def test_unplanted_variants_equal_the_oracle():
         assert np.array_equal(a, b)
     assert np.array_equal(_moments()(st), twa.moments(st))
     assert np.array_equal(_pump_matrix()(9, 1.3, 0.9), pump.pump_matrix(9, 1.3, 0.9))
+    dst = tuple(rng.standard_normal((B, n)) for _ in range(3))
+    fl = twa.fields(st, p.W, gamma, dt, dxi, dchi)
+    for a, b in zip(_increment_tangent()(st, dst, fl, p.W, gamma, dt), twa.increment_tangent(st, dst, fl, p.W, gamma, dt)):
+        assert np.array_equal(a, b)
+    Wn = rng.standard_normal((n, n))
+    for a, b in zip(_incr_vjp()(st, dst, fl, Wn, gamma, dt), ograd._incr_vjp(st, dst, fl, Wn, gamma, dt)):
+        assert np.array_equal(a, b)
+    assert np.array_equal(_first_column()(130, 1.7, 0.8), toeplitz.first_column(130, 1.7, 0.8))
+    q = rng.standard_normal((9, 5))
+    for a, b in zip(_decay_derived()(q), odecay.derived(q)):
+        assert np.array_equal(a, b)
+    corr = np.exp(-0.3 * np.arange(64)) * (1 + 0.1j)
+    for a, b in zip(_spectrum()(corr, 0.05), observables.spectrum(corr, 0.05)):
+        assert np.array_equal(a, b)
     words = philox.philox4x32_10(np.arange(64, dtype=np.uint64), 1, 2, 3, 4, 5)
     for a, b in zip(_box_muller()(words[0], words[1]), philox.box_muller(words[0], words[1])):
         assert np.array_equal(a, b)
