@@ -183,6 +183,11 @@ __device__ __forceinline__ Rsrc wave_rsrc(const void* base, int64_t bytes) {
     const uint32_t n = bytes >= (int64_t)0xFFFFFFFF ? 0xFFFFFFFFu : (uint32_t)bytes;
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)n, 0x00020000);
 }
+// 16 bytes per lane from a raw buffer straight into LDS (lane i to byte 16 i
+// of the 1 KB at lds); a MUBUF load, which the compiler counts in vmcnt only
+__device__ __forceinline__ void buffer_dma16(Rsrc r, void* lds, uint32_t voff) {
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (__attribute__((address_space(3))) void*)lds, 16, voff, 0, 0, 0);
+}
 template <typename S>
 __device__ __forceinline__ void bld4(Rsrc r, uint32_t voff, uint32_t soff, S (&v)[4]) {
     if constexpr (sizeof(S) == 4) {
@@ -345,9 +350,17 @@ __device__ __forceinline__ void stage_tile(const GemmArgs<PREC>& a, const int mt
     const char* Xg = reinterpret_cast<const char*>(a.X + cp * a.x_copy + n0 * a.ldx);
     const int64_t ldx_b = a.ldx * (int64_t)sizeof(G);
     const int nk = (int)(a.K / KT);
-    // Direct global -> LDS loads (global_load_lds_dwordx4): one wave
+    // Direct memory -> LDS loads (buffer_load_dwordx4 ... lds): one wave
     // instruction moves 64 x 16 bytes into 1 KB of LDS, lane i to offset 16 i,
-    // so each lane fetches the global piece that belongs at its slot.
+    // so each lane fetches the piece that belongs at its slot.  The buffer
+    // form, not global_load_lds: the compiler takes a FLAT-encoded load into
+    // LDS for a possible out-of-order LDS access and then waits for every
+    // fragment read before the first MFMA of a stage (lgkmcnt(0)); with the
+    // buffer form it waits for each read only where its MFMA needs it.  A
+    // stage's descriptors span exactly this tile's rows of that stage (A:
+    // MT rows of KB bytes; X: NT rows at a pitch of ldx elements), so no
+    // load can leave them; the offsets fit 32 bits for any A that fits in
+    // device memory.
     constexpr int RPC = 1024 / KB;                 // rows per 1 KB chunk
     constexpr int NCH = (MT + NT) / RPC;           // chunks per stage
     constexpr int NWV = NTHR / 64;
@@ -361,7 +374,7 @@ __device__ __forceinline__ void stage_tile(const GemmArgs<PREC>& a, const int mt
         return PREC == TWA_PREC_FP64 ? (r16 ^ (r16 >> 2)) % PCS : (PCS >= 16 ? r16 : r16 >> 1) % PCS;
     };
     const int wv = __builtin_amdgcn_readfirstlane(wave);
-    const char* src[CPW];
+    uint32_t voff[CPW];           // lane's byte offset in its chunk's operand rows of one stage
     bool srcA[CPW];               // chunk j holds rows of A (else of X); wave-uniform
 #pragma unroll
     for (int j = 0; j < CPW; ++j) {
@@ -369,17 +382,17 @@ __device__ __forceinline__ void stage_tile(const GemmArgs<PREC>& a, const int mt
         const int row = q * RPC + lane / PCS;
         const int pc = (lane % PCS) ^ swz(row & 15);
         srcA[j] = q * RPC < MT;
-        src[j] = row < MT ? Ag + row * KB + pc * 16 : Xg + (int64_t)(row - MT) * ldx_b + pc * 16;
+        voff[j] = row < MT ? (uint32_t)(row * KB + pc * 16) : (uint32_t)((row - MT) * ldx_b + pc * 16);
     }
     const int64_t astage_b = P * KB;   // bytes between K stages of A
-    typedef __attribute__((address_space(3))) char lds_t;
-    typedef const __attribute__((address_space(1))) void gptr_t;
+    const int64_t a_stage_bytes = (int64_t)MT * KB;               // this tile's A rows of one stage
+    const int64_t x_stage_bytes = (int64_t)(NT - 1) * ldx_b + KB; // its X rows of one stage
 #define TWA_DMA(KT_, BUF_)                                                                              \
     do {                                                                                                \
-        const int64_t kofs_ = (int64_t)(KT_) * KB, aofs_ = (int64_t)(KT_) * astage_b;                   \
+        const Rsrc ra_ = wave_rsrc(Ag + (int64_t)(KT_) * astage_b, a_stage_bytes);                      \
+        const Rsrc rx_ = wave_rsrc(Xg + (int64_t)(KT_) * KB, x_stage_bytes);                            \
         _Pragma("unroll") for (int j = 0; j < CPW; ++j) if (CPW == CPWMIN || wv + j * NWV < NCH)        \
-            __builtin_amdgcn_global_load_lds((gptr_t*)(src[j] + (srcA[j] ? aofs_ : kofs_)),             \
-                                             (lds_t*)((BUF_) + (wv + j * NWV) * 1024), 16, 0, 0);       \
+            buffer_dma16(srcA[j] ? ra_ : rx_, (BUF_) + (wv + j * NWV) * 1024, voff[j]);                  \
     } while (0)
 
     // fragment read offsets of this lane (row within a 16-row block, swizzle)
