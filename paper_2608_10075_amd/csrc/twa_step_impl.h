@@ -1091,9 +1091,21 @@ TWA_CFG(6, 256, 128, 64, 4, 2, 4)
 TWA_CFG(7, 320, 256, 128, 4, 2, 2)
 TWA_CFG(8, 320, 256, 64, 4, 2, 4)
 
+// The contraction loop reaches a stage's X rows by 32-bit byte offsets from
+// the stage's base: NT - 1 rows at a pitch of ldx elements plus one K stage
+// must stay within 4 GiB (beyond it the buffer loads would return zeros).
+template <int PREC>
+static bool x_offsets_fit(int64_t ldx, int nt, int kbytes) {
+    return (int64_t)(nt - 1) * ldx * (int64_t)sizeof(typename Prec<PREC>::G) + kbytes <= (int64_t)0xFFFFFFFF;
+}
+
 template <int PREC, int CFG, int STAGE, int KIND>
 static int launch_kernel(const GemmArgs<PREC>& a, int64_t P, int64_t C2, int ncopy, hipStream_t st) {
     typedef CfgT<PREC, CFG> C;
+    if (!x_offsets_fit<PREC>(a.ldx, C::NT, C::KB)) {
+        set_error("operand pitch too large for the contraction's 32-bit offsets");
+        return TWA_EINVAL;
+    }
     GemmArgs<PREC> aa = a;
     aa.nnt = (int)(C2 / C::NT);
     dim3 grid((unsigned)((P / C::MT) * (C2 / C::NT)), 1u, (unsigned)ncopy);
@@ -1386,6 +1398,10 @@ int grouped_prepare_p(const std::vector<Geometry>& gs, const std::vector<Ensembl
                     h[(size_t)p] = make_args<PREC>(gs[(size_t)p], bs[(size_t)p], cs[(size_t)p], stage, tan, cur,
                                                    win && stage == 2, win || tan);
                     h[(size_t)p].nnt = (int)(gs[(size_t)p].C2 / tc.nt);
+                    if (!x_offsets_fit<PREC>(h[(size_t)p].ldx, tc.nt, tc.kbytes)) {
+                        set_error("operand pitch too large for the contraction's 32-bit offsets");
+                        return TWA_EINVAL;
+                    }
                 }
                 TWA_HIP_CHECK(hipMalloc(&pl.d_args[v][stage - 1][cur], h.size() * sizeof(GemmArgs<PREC>)));
                 TWA_HIP_CHECK(hipMemcpyAsync(pl.d_args[v][stage - 1][cur], h.data(), h.size() * sizeof(GemmArgs<PREC>),
