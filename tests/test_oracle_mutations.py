@@ -17,9 +17,10 @@ import pytest
 
 from oracle import decay as odecay
 from oracle import grad as ograd
-from oracle import observables, philox, protocol, pump, toeplitz, twa
+from oracle import closed_forms, observables, philox, protocol, pump, toeplitz, twa
 from tests import test_oracle_decay as tdecay
 from tests import test_oracle_dynamics as dyn
+from tests import test_oracle_exchange as texch
 from tests import test_oracle_grad as tgrad
 from tests import test_oracle_protocol as tproto
 from tests import test_oracle_pump as tpump
@@ -33,8 +34,8 @@ GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 # ---- variants of the oracle's functions, each with one switchable mistake
 
-def _increment(flip_pump=False, drop_collective=False, flip_z=False, y_field_from_x=False):
-    """Eq. (S1) increment (no coherent exchange)."""
+def _increment(flip_pump=False, drop_collective=False, flip_z=False, y_field_from_x=False, flip_exchange=False):
+    """Eq. (S1) increment, with the coherent exchange terms when W carries them."""
     def increment(state, W, gamma, dt, dxi, dchi):
         x, y, z = state
         Sx = x.sum(axis=1)[:, None]
@@ -43,6 +44,14 @@ def _increment(flip_pump=False, drop_collective=False, flip_z=False, y_field_fro
         sgn = 0.5 if flip_pump else -0.5
         hx = (c * Sx + sgn * twa._matvec(W, x)) * dt + dxi[0][:, None] - dchi[0]
         hy = (c * Sy + sgn * twa._matvec(W, x if y_field_from_x else y)) * dt + dxi[1][:, None] - dchi[1]
+        om = getattr(W, "omega", None)
+        if om is not None:
+            if flip_exchange:
+                hx = hx - dt * (y @ om.T)
+                hy = hy + dt * (x @ om.T)
+            else:
+                hx = hx + dt * (y @ om.T)
+                hy = hy - dt * (x @ om.T)
         dz = (x * hx + y * hy) if flip_z else -(x * hx + y * hy)
         return z * hx, z * hy, dz, (hx, hy)
     return increment
@@ -199,6 +208,91 @@ def _spectrum(factor=2.0):
     return spectrum
 
 
+def _model_pump(drift_plus=False, noise_from_w=False):
+    """Drift W - G and noise factor sqrt(W + G) of the correlated-decay step."""
+    def model_pump(W, G):
+        W = np.asarray(W, dtype=np.float64)
+        G = np.asarray(G, dtype=np.float64)
+        M = W + G
+        lam, V = np.linalg.eigh(M)
+        return pump.Pump(W.shape[0], float("nan"), float("nan"), W + G if drift_plus else W - G,
+                         odecay.factor(W if noise_from_w else M), lam, V, float(lam[0]), float(lam[-1]))
+    return model_pump
+
+
+def _general_quantities(q3_slip=False):
+    """The nine per-trajectory quantities of the correlated-emission estimator."""
+    def general_quantities(state, G):
+        x, y, z = state
+        sp = 0.5 * (x + 1j * y)
+        sm = 0.5 * (x - 1j * y)
+        dg = np.diag(G)
+        Gsm = sm @ G.T
+        GTsp = sp @ G
+        E2 = np.sum(sp * Gsm, axis=1).real
+        D = z @ dg
+        Q3 = np.sum(z * (Gsm if q3_slip else GTsp) * Gsm, axis=1).real
+        R = z @ (dg * dg)
+        U = np.sum(z * (z @ (G * G.T).T), axis=1)
+        V = np.sum(dg * sp * Gsm, axis=1).real
+        return np.stack([E2, E2 * E2, E2 * D, Q3, R, D * D, U, V, D], axis=1)
+    return general_quantities
+
+
+def _toeplitz_noise(drop_m=False):
+    def noise(self, eps):
+        scale = self.lam_plus if drop_m else self.lam_plus * self.M
+        eta = np.fft.ifft(np.sqrt(scale)[None, :] * eps, axis=1)[:, :self.n_spin]
+        return eta.real, eta.imag
+    return noise
+
+
+def _stationary_alpha0(flip_k=False):
+    """Exact stationary TWA moments at alpha = 0 (the law of the rigidly
+    rotating collective spin, exp(-k u) on u = cos theta)."""
+    def stationary_alpha0(n_spin, gamma, w):
+        vals, prob = closed_forms._rademacher_sum_law(n_spin)
+        nodes, weights = np.polynomial.legendre.leggauss(200)
+        acc = np.zeros(5)
+        for X, pX in zip(vals, prob):
+            for Y, pY in zip(vals, prob):
+                R = np.sqrt(X * X + Y * Y + n_spin * n_spin)
+                k = (gamma - w) * R / (gamma + w)
+                E = closed_forms._u_moments(-k if flip_k else k, nodes, weights)
+                s2 = 1.0 - nodes ** 2
+                T2 = R ** 2 * E(s2) / 4.0
+                T3 = R ** 3 * E(s2 * nodes) / 4.0
+                T4 = R ** 4 * E(s2 ** 2) / 16.0
+                Zm = R * E(nodes)
+                ZZ = R ** 2 * E(nodes ** 2)
+                acc += pX * pY * np.array([T2, T3, T4, Zm, ZZ])
+        return acc
+    return stationary_alpha0
+
+
+def _dfactor(one_sided=False):
+    """Derivative of the PSD square root along dW (Sylvester equation F X + X F = dW)."""
+    def dfactor(p, dW):
+        tol = 8.0 * p.n_spin * np.finfo(np.float64).eps * max(p.lam_max, 0.0)
+        r = np.sqrt(np.where(p.lam > tol, p.lam, 0.0))
+        B = p.V.T @ dW @ p.V
+        den = 2.0 * r[:, None] + 0.0 * r[None, :] if one_sided else r[:, None] + r[None, :]
+        Xp = np.where(den > 0, B / np.where(den > 0, den, 1.0), 0.0)
+        X = p.V @ Xp @ p.V.T
+        return 0.5 * (X + X.T)
+    return dfactor
+
+
+def _collective_noise(pump_tag=False):
+    def collective_noise(seed, step, n_traj, point=0, traj=None):
+        k0, k1 = philox.seed_key(seed)
+        k = philox._traj_index(n_traj, traj)
+        tag = philox.TAG_PUMP if pump_tag else philox.TAG_COLLECTIVE
+        x0, x1, _, _ = philox.philox4x32_10(np.uint64(0), k, np.uint64(step), philox._tagword(tag, point), k0, k1)
+        return philox.box_muller(x0, x1)
+    return collective_noise
+
+
 _REAL_PROTOCOL = protocol.protocol
 
 
@@ -337,6 +431,32 @@ CASES = {
     "linewidth taken at a quarter of the maximum": (
         [(observables, "fwhm", _quarter)],
         [tstat.test_spectrum_of_exponential_has_fwhm_two_gamma]),
+    "correlated-decay drift W + G instead of W - G": (
+        [(odecay, "model_pump", _model_pump(drift_plus=True))],
+        [tdecay.test_noiseless_correlated_decay_vs_dop853,
+         lambda: tdecay.test_sz_rate_at_t0_matches_lindblad_with_correlated_decay(3, True, "free")]),
+    "correlated-decay noise from W alone": (
+        [(odecay, "model_pump", _model_pump(noise_from_w=True))],
+        [tdecay.test_noise_covariance_is_pump_plus_decay]),
+    "Q3 of the correlated-emission estimator with a slipped index": (
+        [(odecay, "general_quantities", _general_quantities(q3_slip=True))],
+        [tdecay.test_quantities_equal_brute_force_index_sums]),
+    "coherent exchange field with the wrong sign": (
+        [(twa, "increment", _increment(flip_exchange=True))],
+        [texch.test_first_moments_at_t0_equal_the_heisenberg_rates_of_a_product_state,
+         texch.test_noiseless_full_model_vs_dop853]),
+    "circulant noise without the factor M": (
+        [(toeplitz.ToeplitzPump, "noise", _toeplitz_noise(drop_m=True))],
+        [ttoep.test_noise_covariance_is_the_pump]),
+    "alpha = 0 stationary law with the wrong sign of k": (
+        [(closed_forms, "stationary_alpha0", _stationary_alpha0(flip_k=True))],
+        [tstat.test_alpha0_stationary_law_monte_carlo]),
+    "square-root derivative with a one-sided denominator": (
+        [(pump, "dfactor", _dfactor(one_sided=True))],
+        [tpump.test_sylvester_factor_derivative]),
+    "collective noise drawn on the pump stream": (
+        [(philox, "collective_noise", _collective_noise(pump_tag=True))],
+        [trng.test_streams_are_distinct_across_tags_points_steps]),
     "d w_ij / d alpha with the wrong sign": (
         [(ograd, "dpump_dalpha", lambda n, w, a: -_REAL_DPUMP(n, w, a))],
         [tgrad.test_pathwise_gradient_matches_central_differences]),
@@ -390,6 +510,27 @@ def test_unplanted_variants_equal_the_oracle():
     assert np.array_equal(_first_column()(130, 1.7, 0.8), toeplitz.first_column(130, 1.7, 0.8))
     q = rng.standard_normal((9, 5))
     for a, b in zip(_decay_derived()(q), odecay.derived(q)):
+        assert np.array_equal(a, b)
+    Gm = rng.standard_normal((n, n))
+    Gm = Gm @ Gm.T / n
+    a_, b_ = _model_pump()(p.W, Gm), odecay.model_pump(p.W, Gm)
+    assert np.array_equal(a_.W, b_.W) and np.array_equal(a_.F, b_.F)
+    assert np.array_equal(_general_quantities()(st, Gm), odecay.general_quantities(st, Gm))
+    om = rng.standard_normal((n, n))
+    om = om + om.T
+    np.fill_diagonal(om, 0.0)
+    ex = odecay.Exchange(p.W, om)
+    for a, b in zip(_increment()(st, ex, gamma, dt, dxi, dchi)[:3], twa.increment(st, ex, gamma, dt, dxi, dchi)[:3]):
+        assert np.array_equal(a, b)
+    tp = toeplitz.ToeplitzPump(130, 1.7, 0.8)
+    eps = tp.normals(3, 5, 4)
+    for a, b in zip(_toeplitz_noise()(tp, eps), tp.noise(eps)):
+        assert np.array_equal(a, b)
+    assert np.array_equal(_stationary_alpha0()(6, 1.0, 0.5), closed_forms.stationary_alpha0(6, 1.0, 0.5))
+    dW = rng.standard_normal((n, n))
+    dW = dW + dW.T
+    assert np.array_equal(_dfactor()(p, dW), pump.dfactor(p, dW))
+    for a, b in zip(_collective_noise()(3, 7, 5), philox.collective_noise(3, 7, 5)):
         assert np.array_equal(a, b)
     corr = np.exp(-0.3 * np.arange(64)) * (1 + 0.1j)
     for a, b in zip(_spectrum()(corr, 0.05), observables.spectrum(corr, 0.05)):
