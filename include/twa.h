@@ -34,7 +34,10 @@
  *     hipGraph capture that another thread has open.  Each call owns its
  *     buffers, pump handles are only read by runs, graphs are captured in
  *     thread-local mode on the call's own stream, and no call issues work on
- *     the null stream (twa_run_noalloc given NULL aside).
+ *     the null stream (twa_run_noalloc given NULL aside).  The lock does not
+ *     extend to other code in the process: a library call that releases
+ *     memory synchronises the device, so it must not overlap a hipGraph
+ *     capture that another thread holds open outside the library.
  *   - All arithmetic of the time stepping runs in the library's HIP kernels
  *     for gfx950.  There is no CPU fallback: without a usable GPU every
  *     compute entry point returns TWA_EHIP.
