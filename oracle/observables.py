@@ -15,7 +15,11 @@ Test infrastructure only; see the package docstring.
   the classical product; the commutator part is
   kappa * i (chi_xx + chi_yy + i chi_yx - i chi_xy) with kappa = 1/4 as printed
   after Eq. (S3) (an alternative reading of the per-component formula gives
-  1/16; both are available).
+  1/16; both are available).  The symmetric part and the responses are
+  pinned by tests; the weight kappa of their combination is fixed by the
+  printed coefficient alone (parity unpinned for that one constant: no
+  limit or closed form fixes it, and in the static limit the printed
+  combination is not exact for any kappa).
 * Spectrum S(omega) = 2 Re int dt e^{i omega t} <S+(t) S-(0)> over t >= 0;
   linewidth = full width at half maximum.
 """
