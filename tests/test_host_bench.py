@@ -65,6 +65,18 @@ def test_traffic_summary_is_per_launch_and_calibrated():
     assert d["bytes_per_launch"] > 0.5e9
 
 
+def test_stage_kernel_summaries_share_one_source():
+    """Every committed summary of the contraction kernels (trace, counters,
+    traffic, the equal-accuracy trace) names the kernel source it was taken
+    on, and all of them name the same one: a partial re-profile fails here."""
+    shas = {json.load(open(os.path.join(ROOT, "profiles", "stage1_traffic_n1e4_bf16_sib.json")))["source_sha"]}
+    for f in glob.glob(os.path.join(ROOT, "profiles", "stage_kernels_*.md")):
+        m = re.findall(r"Source hash[^`]*`([0-9a-f]{16})`", open(f).read())
+        assert m, f
+        shas |= set(m)
+    assert len(shas) == 1, shas
+
+
 def test_bench_refuses_more_than_one_gpu():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120)
