@@ -293,7 +293,50 @@ def _collective_noise(pump_tag=False):
     return collective_noise
 
 
+def _solve3(replace_row=False):
+    """3 x 3 solves by Cramer's rule: column c of M replaced by r."""
+    def solve3(M, r):
+        def det(A):
+            return (A[..., 0, 0] * (A[..., 1, 1] * A[..., 2, 2] - A[..., 1, 2] * A[..., 2, 1])
+                    - A[..., 0, 1] * (A[..., 1, 0] * A[..., 2, 2] - A[..., 1, 2] * A[..., 2, 0])
+                    + A[..., 0, 2] * (A[..., 1, 0] * A[..., 2, 1] - A[..., 1, 1] * A[..., 2, 0]))
+        d = det(M)
+        out = []
+        for c in range(3):
+            Mc = M.copy()
+            if replace_row:
+                Mc[..., c, :] = r
+            else:
+                Mc[..., :, c] = r
+            out.append(det(Mc) / d)
+        return out
+    return solve3
+
+
+def _t3_from_sz_squared(state):
+    Sx, Sy, Sz = twa.collective_sums(*state)
+    T2 = 0.25 * (Sx * Sx + Sy * Sy)
+    return np.stack([T2, T2 * Sz * Sz, T2 * T2, Sz, Sz * Sz], axis=1)
+
+
+def _finalize_round_robin_blocks(traj_moments):
+    """The jackknife with trajectory k in block k mod J instead of the
+    contiguous block floor(k J / B)."""
+    B = traj_moments.shape[0]
+    J = min(32, B)
+    order = np.argsort(np.arange(B) % J, kind="stable")
+    return _REAL_FINALIZE(traj_moments[order])
+
+
 _REAL_PROTOCOL = protocol.protocol
+
+
+def _protocol_tau_s_from_lam_min(N, w, alpha, gamma=1.0, cfl=0.04, finite_size=False, pump=None):
+    pr = _REAL_PROTOCOL(N, w, alpha, gamma, cfl, finite_size, pump)
+    if finite_size or alpha >= 1.0:
+        return pr
+    tau_s = 10.0 / pr.lam_min
+    return dataclasses.replace(pr, tau_s=tau_s, n_prep=int(np.ceil(tau_s / pr.dt - 1e-9)))
 
 
 def _protocol_without_gamma_n(N, w, alpha, gamma=1.0, cfl=0.04, finite_size=False, pump=None):
@@ -457,6 +500,18 @@ CASES = {
     "collective noise drawn on the pump stream": (
         [(philox, "collective_noise", _collective_noise(pump_tag=True))],
         [trng.test_streams_are_distinct_across_tags_points_steps]),
+    "Cramer's rule with a row instead of a column replaced": (
+        [(twa, "_solve3", _solve3(replace_row=True))],
+        [tsib.test_midpoint_stage_is_the_rotation_about_minus_b]),
+    "T3 built from (S^z)^2 instead of S^z": (
+        [(twa, "moments", _t3_from_sz_squared)],
+        [tstat.test_alpha0_stationary_law_monte_carlo]),
+    "jackknife blocks round-robin instead of contiguous": (
+        [(observables, "finalize", _finalize_round_robin_blocks)],
+        [tstat.test_jackknife_se_of_mean_matches_block_standard_error]),
+    "preparation time 10 / lambda_min also for alpha < 1": (
+        [(protocol, "protocol", _protocol_tau_s_from_lam_min)],
+        [tproto.test_step_criterion_and_times]),
     "d w_ij / d alpha with the wrong sign": (
         [(ograd, "dpump_dalpha", lambda n, w, a: -_REAL_DPUMP(n, w, a))],
         [tgrad.test_pathwise_gradient_matches_central_differences]),
@@ -500,6 +555,10 @@ def test_unplanted_variants_equal_the_oracle():
         assert np.array_equal(a, b)
     assert np.array_equal(_moments()(st), twa.moments(st))
     assert np.array_equal(_pump_matrix()(9, 1.3, 0.9), pump.pump_matrix(9, 1.3, 0.9))
+    Mq = rng.standard_normal((4, 3, 3)) + 3 * np.eye(3)
+    rq = rng.standard_normal((4, 3))
+    for a, b in zip(_solve3()(Mq, rq), twa._solve3(Mq, rq)):
+        assert np.array_equal(a, b)
     dst = tuple(rng.standard_normal((B, n)) for _ in range(3))
     fl = twa.fields(st, p.W, gamma, dt, dxi, dchi)
     for a, b in zip(_increment_tangent()(st, dst, fl, p.W, gamma, dt), twa.increment_tangent(st, dst, fl, p.W, gamma, dt)):
