@@ -130,6 +130,22 @@ def test_headline_fp32_error_is_fp64_error_at_fp32_rounding(twa, headline, integ
     assert r32 < 2.0 * ratio * r64, (r32, r64)
 
 
+def test_headline_split_bf16_error_is_fp64_error_at_its_rounding(twa, headline):
+    """The equal-accuracy mode over 10^3 steps of the headline workload
+    (semi-implicit): split BF16 represents each contracted increment to about
+    2^-16 relative (operands to 2^-17, the dropped lo x lo product below
+    2^-18), so under the same amplification of rounding its error against the
+    oracle stays within the FP64 path's error scaled by 2^-16 / 2^-53, with a
+    factor 2 as for FP32; it must also beat plain BF16 on the same steps."""
+    r3, _ = _compare(twa, headline, "sib", "bf16x3", 1000)
+    r64, _ = _compare(twa, headline, "sib", "fp64", 1000)
+    r16, _ = _compare(twa, headline, "sib", "bf16", 1000)
+    ratio = 2.0 ** -16 / 2.0 ** -53
+    print("sib: bf16x3 %.3e, bf16 %.3e, fp64 %.3e, fp64 x u16/u64 = %.3e" % (r3, r16, r64, r64 * ratio))
+    assert r3 < 2.0 * ratio * r64, (r3, r64)
+    assert r3 < r16 / 10, (r3, r16)
+
+
 def test_fp64_workload_n16_all_trajectories_and_ensemble(twa):
     N, alpha, w, B, dt, T = 16, 1.0, 4.0, 512, 1e-3, 20000
     pump = twa.build_pump(N, w, alpha)
